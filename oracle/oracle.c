@@ -102,21 +102,33 @@ int orc_basis(int dim, int p, const double *lo, const double *hi, const double *
 }
 
 /* ------------------------------------------------- coefficients and data */
+/* sin(pi x) and cos(pi x) with the argument reduced exactly (shifts by whole
+ * periods are exact in binary floating point), so that sin(pi k) = 0 and
+ * cos(pi (k + 1/2)) = 0 hold exactly at integer and half-integer points. */
+static double sinpi_(double x) {
+    double r = x - 2.0 * floor(0.5 * x); /* [0, 2) */
+    if (r > 1.5) return sin(PI * (r - 2.0));
+    if (r > 0.5) return sin(PI * (1.0 - r));
+    return sin(PI * r);
+}
+
+static double cospi_(double x) { return sinpi_(x + 0.5); }
+
 static double coef_a(const orc_problem *pr, const double *x) {
-    return pr->a0 + pr->a1 * sin(2 * PI * x[0]) * cos(2 * PI * x[1]);
+    return pr->a0 + pr->a1 * sinpi_(2 * x[0]) * cospi_(2 * x[1]);
 }
 
 static void coef_grad_a(const orc_problem *pr, const double *x, double *g) {
-    g[0] = pr->a1 * 2 * PI * cos(2 * PI * x[0]) * cos(2 * PI * x[1]);
-    g[1] = -pr->a1 * 2 * PI * sin(2 * PI * x[0]) * sin(2 * PI * x[1]);
+    g[0] = pr->a1 * 2 * PI * cospi_(2 * x[0]) * cospi_(2 * x[1]);
+    g[1] = -pr->a1 * 2 * PI * sinpi_(2 * x[0]) * sinpi_(2 * x[1]);
     g[2] = 0.0;
 }
 
 static void exact_u(const orc_problem *pr, int dim, const double *x, double *u, double *gu, double *lap) {
     double X = x[0], Y = x[1], Z = dim == 3 ? x[2] : 0.0;
     if (pr->u_kind == ORC_U_SIN) {
-        double sx = sin(PI * X), cx = cos(PI * X), sy = sin(PI * Y), cy = cos(PI * Y);
-        double sz = dim == 3 ? sin(PI * Z) : 1.0, cz = dim == 3 ? cos(PI * Z) : 0.0;
+        double sx = sinpi_(X), cx = cospi_(X), sy = sinpi_(Y), cy = cospi_(Y);
+        double sz = dim == 3 ? sinpi_(Z) : 1.0, cz = dim == 3 ? cospi_(Z) : 0.0;
         *u = sx * sy * sz;
         gu[0] = PI * cx * sy * sz;
         gu[1] = PI * sx * cy * sz;

@@ -1,0 +1,135 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Pattern arrays bit-exact; values per block within 1e-12 (FP64 path) or 1e-5
+(FP32 path) relative Frobenius error, the right-hand side per element row the
+same.  Sizes span many work-groups and a ragged last one; the headline
+workload (16,384 cells, p = 2, variable diffusion, advection, reaction) is
+checked in full, in the launch configuration the benchmark times.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from meshgen import cartesian_mesh, config_mesh, problem_params, voronoi_mesh
+from tests.parity import TOL, block_errors, check_pattern, gpu_assemble, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+DAR = dict(a0=1.0, a1=0.5, b=(1.0, 0.5, 0.0), c=1.0, c_sigma=10.0, u="sin")
+POISSON = dict(a0=1.0, a1=0.0, b=(0.0, 0.0, 0.0), c=0.0, c_sigma=10.0, u="sin")
+POLY = dict(a0=1.3, a1=0.0, b=(0.4, -0.7, 0.0), c=0.9, c_sigma=10.0, u="poly",
+            u_poly=(1.0, 2.0, -1.0, 0.0, 1.0, -0.5, 0.0, 1.0, 0.0, 0.0))
+
+
+def _case(mesh, params, precision, full_path=False):
+    print(f"[case] {mesh.name} p={sorted(set(mesh.cell_p.tolist()))} prec={precision} full={full_path}", flush=True)
+    pat = oracle.pattern(mesh)
+    g = gpu_assemble(mesh, params, precision, full_path)
+    check_pattern(g, pat)
+    vals, rhs = oracle.assemble(mesh, oracle_problem(params), pat=pat)
+    eb, er = block_errors(g, vals, rhs, pat)
+    print(f"       worst block {eb:.3e}  worst rhs row {er:.3e}", flush=True)
+    assert eb <= TOL[precision], eb
+    assert er <= TOL[precision], er
+    return g
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_workload1_64_cells(precision):
+    _case(config_mesh(1), problem_params(1), precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_workload2_full_size(precision):
+    _case(config_mesh(2), problem_params(2), precision)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_voronoi_degrees(p, precision):
+    # 1000 cells: 32 rows per FP32 work-group -> a ragged last work-group
+    m = voronoi_mesh(1000, 77, lloyd=1, p=p)
+    _case(m, DAR, precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_polynomial_data_and_full_path(precision):
+    m = voronoi_mesh(333, 78, lloyd=2, p=2)
+    _case(m, POLY, precision, full_path=True)
+
+
+def test_cartesian_and_neumann():
+    m = cartesian_mesh(7, 5, p=2, x0=0.1, x1=1.3, y0=-0.2, y1=0.9)
+    _case(m, DAR, 0)
+    # turn the faces on the left side into Neumann faces
+    m2 = cartesian_mesh(7, 5, p=2)
+    xl = np.where(m2.x == 0.0)[0]
+    fv = m2.face_vtx.reshape(-1, 2)
+    left = np.isin(fv[:, 0], xl) & np.isin(fv[:, 1], xl)
+    m2.face_bc[left] = 2
+    _case(m2, DAR, 0)
+
+
+def test_single_cell_and_tiny():
+    m = cartesian_mesh(1, 1, p=2)
+    _case(m, DAR, 0)
+    _case(voronoi_mesh(5, 3, p=1), POISSON, 1)
+
+
+def test_deterministic_and_graph_replay():
+    import torch
+    import paper_2007_04881_amd as D
+    m = config_mesh(2)
+    params = problem_params(2)
+    ctx = D.Context(0)
+    ctx.upload(m)
+    ctx.pattern()
+    v1, r1 = ctx.outputs(D.F32)
+    ctx.run(params, D.F32, v1, r1)
+    torch.cuda.synchronize()
+    v2, r2 = ctx.outputs(D.F32)
+    ctx.assemble(params, D.F32, v2, r2)
+    torch.cuda.synchronize()
+    assert torch.equal(v1, v2) and torch.equal(r1, r2)
+    for what in (0, 1):
+        v3, r3 = ctx.outputs(D.F32)
+        ctx.graph_capture(what, params, D.F32, v3, r3)
+        for rep in range(3):
+            v3.fill_(-1.0)
+            r3.fill_(-1.0)
+            torch.cuda.synchronize()
+            ctx.graph_launch()
+            torch.cuda.synchronize()
+            assert torch.equal(v1, v3) and torch.equal(r1, r3), (what, rep)
+    ctx.close()
+
+
+def test_error_paths():
+    import paper_2007_04881_amd as D
+    ctx = D.Context(0)
+    with pytest.raises(D.DgpError) as e:
+        ctx.pattern()
+    assert e.value.status == -6
+    m = voronoi_mesh(50, 5, p=2)
+    bad = m.with_degrees(2)
+    bad.cell_vtx = bad.cell_vtx.copy()
+    bad.cell_vtx[3] = bad.n_vertices + 5
+    with pytest.raises(D.DgpError) as e:
+        ctx.upload(bad)
+    assert e.value.status == -2
+    bad = m.with_degrees(2)
+    bad.face_cell = bad.face_cell.copy()
+    f = int(np.where(bad.face_cell[1::2] >= 0)[0][0])
+    bad.face_cell[2 * f + 1] = (bad.face_cell[2 * f] + 7) % bad.n_cells
+    with pytest.raises(D.DgpError):
+        ctx.upload(bad)
+    with pytest.raises(D.DgpError) as e:
+        ctx.upload(m.with_degrees(7))
+    assert e.value.status == -3
+    ctx.upload(m)
+    ctx.pattern()
+    v, r = ctx.outputs(D.F32)
+    with pytest.raises(ValueError):
+        ctx.assemble(DAR, D.F64, v, r)
+    ctx.close()

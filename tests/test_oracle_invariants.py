@@ -168,3 +168,26 @@ def test_penalty_is_max_over_sides():
                              geo["abar"][c] * m.cell_p[c] ** 2 / geo["diam"][c])
             mass = w1[sl] - w0[sl]  # = - int phi'_j phi_i over the shared face
             assert np.allclose(v2[sl] - v1[sl], sig * mass, rtol=1e-9, atol=1e-9 * np.abs(v1[sl]).max())
+
+
+def test_manufactured_load_matches_the_pde():
+    """f = -div(a grad u) + b.grad u + c u (equation CDR) against central
+    differences of u and a computed here with numpy; u vanishes exactly on the
+    boundary of the unit square (the Dirichlet data)."""
+    prob = oracle.Problem(a0=1.0, a1=0.5, b=(1.0, 0.5, 0.0), c=1.0)
+    u = lambda x, y: np.sin(np.pi * x) * np.sin(np.pi * y)
+    a = lambda x, y: 1.0 + 0.5 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+    h = 1e-4
+    rng = np.random.default_rng(4)
+    for x, y in rng.random((20, 2)):
+        flux_x = lambda s, t: a(s, t) * (u(s + h, t) - u(s - h, t)) / (2 * h)
+        flux_y = lambda s, t: a(s, t) * (u(s, t + h) - u(s, t - h)) / (2 * h)
+        div = (flux_x(x + h, y) - flux_x(x - h, y)) / (2 * h) + (flux_y(x, y + h) - flux_y(x, y - h)) / (2 * h)
+        ux = (u(x + h, y) - u(x - h, y)) / (2 * h)
+        uy = (u(x, y + h) - u(x, y - h)) / (2 * h)
+        f_fd = -div + 1.0 * ux + 0.5 * uy + 1.0 * u(x, y)
+        uu, f = oracle.exact(prob, 2, np.array([x, y]))
+        assert abs(uu - u(x, y)) < 1e-15
+        assert abs(f - f_fd) < 1e-5 * max(1.0, abs(f))
+    for x, y in ((0.0, 0.37), (1.0, 0.81), (0.42, 0.0), (0.77, 1.0), (1.0, 1.0)):
+        assert oracle.exact(prob, 2, np.array([x, y]))[0] == 0.0
