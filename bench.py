@@ -1,0 +1,155 @@
+#!/usr/bin/env python3
+"""Benchmark: SIPG assembly throughput on one MI355X.
+
+Workload: 2D diffusion-advection-reaction, 16,384-cell seeded Voronoi mesh of
+the unit square, p = 2 (6 dofs per cell), a = 1 + 0.5 sin(2 pi x) cos(2 pi y),
+b = (1, 0.5), c = 1, upwinded advection faces; contraction and output in FP32,
+geometry, weights and penalty in FP64.
+
+One step = the whole path on the device: block sparsity pattern, geometry,
+assembly of every block row and the right-hand side, replayed from a captured
+HIP graph.  The mesh is resident in HBM before the timed region.  Prints one
+JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def algorithmic_bytes(mesh, info, val_bytes):
+    """Bytes the assembly kernel must move at least once: mesh connectivity and
+    coordinates, per-cell geometry records, the pattern it reads, and the values
+    and right-hand side it writes."""
+    V, N, F = mesh.n_vertices, mesh.n_cells, mesh.n_faces
+    nv = int(mesh.cell_ptr[-1])
+    reads = 16 * V + 8 * (N + 1) + 4 * nv + 4 * nv + 8 * F + F + 64 * N
+    reads += 8 * (N + 1) + 4 * info.nnzb + 8 * (info.nnzb + 1) + 8 * (N + 1)
+    writes = val_bytes * (info.n_vals + info.n_dofs)
+    return reads + writes
+
+
+def cpu_baseline(mesh, params, budget_s=12.0):
+    """The oracle as it stands (single-threaded FP64 C) on the same mesh:
+    pattern + full assembly, repeated until about budget_s seconds of work."""
+    import oracle
+    prob = oracle.Problem.from_params(params)
+    reps, t_total, nnzb = 0, 0.0, 0
+    while t_total < budget_s and reps < 200:
+        t0 = time.perf_counter()
+        pat = oracle.pattern(mesh)
+        oracle.assemble(mesh, prob, pat=pat)
+        t_total += time.perf_counter() - t0
+        nnzb = pat.nnzb
+        reps += 1
+    return dict(value=nnzb * reps / t_total, unit="block-nnz/s", cores=1, kind="oracle",
+                sample=f"{reps} full passes (pattern + assembly) over the same 16,384-cell mesh, "
+                       f"{t_total:.1f} s, single thread",
+                elements_per_s=mesh.n_cells * reps / t_total)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build assembles on exactly one GPU (the method needs no communication; "
+              "the multi-GPU layout is described in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2007_04881_amd as D
+    from meshgen import config_mesh, problem_params
+
+    mesh = config_mesh(2)
+    params = problem_params(2)
+    ctx = D.Context(0)
+    ctx.upload(mesh)
+    info = ctx.pattern()
+    vals, rhs = ctx.outputs(D.F32)
+
+    # single-shot latency of the eager path (pattern + geometry + assembly)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.run(params, D.F32, vals, rhs)
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t0) * 1e3
+
+    # the timed steps: replays of the captured whole path
+    ctx.graph_capture(0, params, D.F32, vals, rhs)
+    for _ in range(args.warmup):
+        ctx.graph_launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.graph_launch()
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    ms_per_step = t_steps * 1e3 / args.steps
+
+    # values only (pattern reused), as in time stepping with changing coefficients
+    ctx.graph_capture(1, params, D.F32, vals, rhs)
+    for _ in range(args.warmup):
+        ctx.graph_launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.graph_launch()
+    torch.cuda.synchronize()
+    ms_values = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    # per-kernel device time from HIP events on the context stream
+    ctx.set_timing(True)
+    kms = {"pattern": [], "geometry": [], "assemble": []}
+    for _ in range(max(20, args.warmup)):
+        ctx.run(params, D.F32, vals, rhs)
+        for k in kms:
+            kms[k].append(ctx.kernel_ms(k))
+    ctx.set_timing(False)
+    avg = {k: sum(v[5:]) / len(v[5:]) for k, v in kms.items()}
+    abytes = algorithmic_bytes(mesh, info, 4)
+    achieved = abytes / (avg["assemble"] * 1e-3) / 1e9
+
+    out = {
+        "metric": "assembled block-nnz/s, 2D Voronoi p=2 (whole path: pattern + geometry + assembly)",
+        "value": info.nnzb * args.steps / t_steps,
+        "unit": "block-nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Voronoi mesh, manufactured solution)",
+        "config": {"workload": "2D DAR, 16384-cell seeded Voronoi, p=2, FP32 contraction with FP64 geometry",
+                   "cells": mesh.n_cells, "nnzb": info.nnzb, "n_vals": info.n_vals, "n_dofs": info.n_dofs,
+                   "parallelism": "single GPU"},
+        "elements_per_s": mesh.n_cells * args.steps / t_steps,
+        "values_only": {"ms_per_step": ms_values, "block_nnz_per_s": info.nnzb / (ms_values * 1e-3)},
+        "single_shot_ms": single_ms,
+        "kernel_ms": avg,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_assemble2d<float,2>", "algorithmic_bytes": abytes},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(mesh, params)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

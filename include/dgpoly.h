@@ -1,0 +1,148 @@
+/*
+ * dgpoly -- SIPG matrix assembly on polytopic meshes for AMD MI355X (gfx950).
+ *
+ * C ABI of libdgpoly.so.  Plain C99: no C++ types and no exceptions cross this
+ * boundary; every call returns a dgp_status.  On any status other than DGP_OK
+ * no output has been written and dgp_last_error() describes the failure.
+ *
+ * What is computed (Dong, Georgoulis, Kappas, "GPU-accelerated discontinuous
+ * Galerkin methods on polytopic meshes"):
+ *   find u_h in S^p with B(u_h, v_h) = l(v_h) for all v_h       (Section 2.2)
+ *   B = the symmetric interior penalty bilinear form   (equation dg-bilinear)
+ *   l = the linear functional                          (equation dg-linear)
+ *   sigma_F = C_sigma * max_{kappa in F} abar_kappa p_kappa^2 / h_kappa
+ *             (Appendix A; h = diameter, abar = max of a over the element's
+ *             volume quadrature points)
+ * with physical-frame orthonormal Legendre bases of total degree p on each
+ * element's bounding box (Section 3.1), quadrature on the fan sub-triangles of
+ * each polygon and Gauss-Legendre points on each edge (Section 3), written into
+ * a precomputed block sparsity pattern (Section 3.4, Approach 2).
+ *
+ * Matrix layout (block CSR, rows = elements):
+ *   row_ptr[n_rows+1]  (int64)  blocks of row r are k = row_ptr[r] .. row_ptr[r+1]-1
+ *   col_idx[nnzb]      (int32)  ascending within a row; the diagonal is present
+ *   val_ptr[nnzb+1]    (int64)  block k occupies vals[val_ptr[k] .. val_ptr[k+1])
+ *   dof_ptr[n_rows+1]  (int64)  rhs entries of row r: rhs[dof_ptr[r] ..]
+ * Block (r, c) is row-major n_b(p_r) x n_b(p_c); entry (i, j) = B(phi_j^c, phi_i^r)
+ * (row = test function, column = trial function).  n_b(p) = (p+1)(p+2)/2 in 2D.
+ * Basis order: total degree k = 0..p, x-exponent descending within k.
+ *
+ * Threading: a context is bound to one device and one HIP stream; it is not
+ * thread-safe.  All device work is asynchronous on that stream unless stated.
+ */
+#ifndef DGPOLY_H
+#define DGPOLY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dgp_status;
+#define DGP_OK 0
+#define DGP_EINVAL (-1)       /* null pointer, size mismatch, bad enum */
+#define DGP_EMESH (-2)        /* malformed mesh: face not adjacent to its cells, bad ids, < 3 vertices */
+#define DGP_EUNSUPPORTED (-3) /* degree or dimension outside what the kernels are built for */
+#define DGP_ENOMEM (-4)       /* device allocation failed */
+#define DGP_EDEVICE (-5)      /* any HIP runtime error */
+#define DGP_ESTATE (-6)       /* call order: e.g. assemble before pattern */
+
+#define DGP_F64 0 /* contraction and output in double precision */
+#define DGP_F32 1 /* geometry, penalty and weights in FP64; contraction and output in FP32 */
+
+#define DGP_U_SIN 0  /* manufactured u = sin(pi x) sin(pi y) */
+#define DGP_U_POLY 1 /* u = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 y^2 + c6 z^2 + c7 xy + c8 xz + c9 yz */
+
+typedef struct dgp_ctx dgp_ctx;
+
+/* Polytopic mesh, host memory; dgp_mesh_upload copies every array (the
+ * caller keeps ownership).  2D only in this version (dim = 2). */
+typedef struct {
+    int32_t dim;
+    int64_t n_vertices;
+    const double *x, *y, *z;      /* [n_vertices]; z may be NULL in 2D */
+    int64_t n_cells;
+    const int64_t *cell_ptr;      /* [n_cells+1] */
+    const int32_t *cell_vtx;      /* counter-clockwise vertex loop; first vertex = fan apex */
+    const int8_t *cell_p;         /* [n_cells] degree, 1..4 */
+    const int64_t *cell_face_ptr; /* [n_cells+1]; 2D: equal to cell_ptr */
+    const int32_t *cell_face;     /* face k of a cell is the edge (v_k, v_{k+1}) of its loop */
+    int64_t n_faces;
+    const int32_t *face_vtx;      /* [2 n_faces] edge vertices, lower id first (canonical order) */
+    const int32_t *face_cell;     /* [2 n_faces] left, right cell; right = -1 on the boundary */
+    const int8_t *face_bc;        /* [n_faces] 0 interior, 1 Dirichlet, 2 Neumann */
+    const int32_t *face_opp;      /* 3D only; may be NULL */
+} dgp_mesh_desc;
+
+/* -div(a grad u) + b . grad u + c u = f, a(x) = a0 + a1 sin(2 pi x) cos(2 pi y);
+ * f, Dirichlet data g_D = u and Neumann data g_N = n . (a grad u) come from the
+ * manufactured u and are evaluated on the device at quadrature points. */
+typedef struct {
+    double a0, a1;
+    double b[3];
+    double c;
+    double c_sigma;    /* penalty constant C_sigma (10 in every workload) */
+    int32_t u_kind;    /* DGP_U_SIN or DGP_U_POLY */
+    double u_poly[10];
+} dgp_problem;
+
+typedef struct {
+    int64_t n_rows, nnzb, n_vals, n_dofs;
+    /* device pointers owned by the context, valid until the next upload or destroy */
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    const int64_t *val_ptr;
+    const int64_t *dof_ptr;
+} dgp_pattern_info;
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL
+ * = the null stream).  Allocates nothing on the device yet. */
+dgp_status dgp_create(dgp_ctx **out, int device, void *hip_stream);
+dgp_status dgp_destroy(dgp_ctx *ctx);
+dgp_status dgp_set_stream(dgp_ctx *ctx, void *hip_stream);
+/* Text of the last failure on this context (static storage inside ctx). */
+const char *dgp_last_error(const dgp_ctx *ctx);
+
+/* Validate the mesh on the host (ids in range, every face listed by its cells,
+ * loops of >= 3 vertices, degrees supported) and copy it to the device.
+ * Synchronous.  Invalidates any previous pattern. */
+dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *mesh);
+
+/* Block sparsity pattern on the device (Section 3.4): row r = sorted unique
+ * {r} U {elements sharing a face with r}.  Synchronous (the sizes are read
+ * back once to allocate); fills *out. */
+dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out);
+
+/* Copy the context's pattern arrays into caller-owned device buffers of the
+ * sizes reported by dgp_pattern (any pointer may be NULL to skip it).
+ * Asynchronous on the context stream. */
+dgp_status dgp_pattern_copy(dgp_ctx *ctx, int64_t *row_ptr, int32_t *col_idx, int64_t *val_ptr, int64_t *dof_ptr);
+
+/* Assemble values and right-hand side into caller-owned device buffers of the
+ * chosen precision: vals[n_vals], rhs[n_dofs] (float or double).  Requires
+ * dgp_pattern.  Asynchronous on the context stream; runs the geometry kernel
+ * (bounding boxes, diameters, abar) and the assembly kernel. */
+dgp_status dgp_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs);
+
+/* The whole path on the device: pattern (recomputed into the context's
+ * arrays, bit-identical), geometry, assembly.  Requires a prior dgp_pattern
+ * (sizes known).  Asynchronous; no host synchronisation. */
+dgp_status dgp_run(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs);
+
+/* Capture dgp_run (what = 0) or dgp_assemble (what = 1) with these arguments
+ * into a HIP graph held by the context, and replay it. */
+dgp_status dgp_graph_capture(dgp_ctx *ctx, int what, const dgp_problem *prob, int precision, void *vals, void *rhs);
+dgp_status dgp_graph_launch(dgp_ctx *ctx);
+
+/* Per-kernel timing of the last dgp_run / dgp_assemble (device milliseconds,
+ * from HIP events recorded on the context stream around each kernel when
+ * timing is enabled).  names: "pattern", "geometry", "assemble". */
+dgp_status dgp_set_timing(dgp_ctx *ctx, int enable);
+dgp_status dgp_kernel_ms(dgp_ctx *ctx, const char *name, float *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

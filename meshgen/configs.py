@@ -52,8 +52,11 @@ def _load(path: str) -> Mesh:
     return Mesh(dim=dim, name=name, **d)
 
 
+GENERATOR_VERSION = "v2"
+
+
 def cached(key: str, build) -> Mesh:
-    path = os.path.join(_cache_dir(), key + ".npz")
+    path = os.path.join(_cache_dir(), f"{key}_{GENERATOR_VERSION}.npz")
     if os.path.exists(path):
         try:
             return _load(path)

@@ -28,7 +28,10 @@ def _morton_key(p: np.ndarray, bits: int = 20) -> np.ndarray:
 def _clipped_regions(pts: np.ndarray):
     """Voronoi vertex array and, per seed, its cyclic vertex list clipped to [0,1]^2."""
     n = pts.shape[0]
-    margin = min(0.5, max(0.05, 24.0 / np.sqrt(n)))
+    # mirror the seeds near each side; small meshes mirror every seed
+    margin = max(0.05, 24.0 / np.sqrt(n))
+    if margin > 0.5:
+        margin = 1.0
     mir = [pts]
     for axis, side in ((0, 0.0), (0, 1.0), (1, 0.0), (1, 1.0)):
         sel = np.abs(pts[:, axis] - side) < margin

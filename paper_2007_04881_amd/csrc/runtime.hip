@@ -1,0 +1,405 @@
+// Host runtime behind the C ABI of include/dgpoly.h: context, mesh upload and
+// validation, device buffers, kernel launches, graph capture and timing.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dgpoly.h"
+#include "dgp_common.h"
+#include "kernels.h"
+
+using namespace dgp;
+
+struct dgp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // used while capturing a graph
+    char err[512] = {0};
+
+    // mesh
+    bool has_mesh = false;
+    int dim = 2;
+    int64_t n_cells = 0, n_faces = 0, n_vertices = 0, n_cell_vtx = 0;
+    int p_uniform = -1;
+    std::vector<void *> mesh_bufs;
+    DevMesh dm{};
+
+    // pattern
+    bool has_pattern = false;
+    int64_t nnzb = 0, n_vals = 0, n_dofs = 0;
+    int64_t *row_ptr = nullptr, *val_ptr = nullptr, *dof_ptr = nullptr;
+    int32_t *col_idx = nullptr;
+    int64_t *tile_sums = nullptr, *totals = nullptr;
+
+    CellGeo *geo = nullptr;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool ev_pattern = false, ev_assemble = false;
+};
+
+static dgp_status fail(dgp_ctx *ctx, dgp_status st, const char *fmt, ...) {
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                                \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) return fail(ctx, DGP_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static void free_pattern(dgp_ctx *c) {
+    for (void *p : {(void *)c->row_ptr, (void *)c->col_idx, (void *)c->val_ptr, (void *)c->dof_ptr})
+        if (p) (void)hipFree(p);
+    c->row_ptr = c->val_ptr = c->dof_ptr = nullptr;
+    c->col_idx = nullptr;
+    c->has_pattern = false;
+}
+
+static void free_graph(dgp_ctx *c) {
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->exec = nullptr;
+    c->graph = nullptr;
+}
+
+static void free_mesh(dgp_ctx *c) {
+    for (void *p : c->mesh_bufs) (void)hipFree(p);
+    c->mesh_bufs.clear();
+    for (void *p : {(void *)c->tile_sums, (void *)c->totals, (void *)c->geo})
+        if (p) (void)hipFree(p);
+    c->tile_sums = c->totals = nullptr;
+    c->geo = nullptr;
+    c->has_mesh = false;
+    free_pattern(c);
+    free_graph(c);
+}
+
+template <typename T>
+static dgp_status upload(dgp_ctx *c, const T *src, int64_t n, const T **dst) {
+    void *p = nullptr;
+    size_t bytes = sizeof(T) * (size_t)(n > 0 ? n : 1);
+    if (hipMalloc(&p, bytes) != hipSuccess) return fail(c, DGP_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    c->mesh_bufs.push_back(p);
+    if (n > 0) HIPCHK(c, hipMemcpy(p, src, sizeof(T) * (size_t)n, hipMemcpyHostToDevice));
+    *dst = static_cast<const T *>(p);
+    return DGP_OK;
+}
+
+extern "C" {
+
+dgp_status dgp_create(dgp_ctx **out, int device, void *hip_stream) {
+    if (!out) return DGP_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DGP_EDEVICE;
+    dgp_ctx *c = new dgp_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return DGP_EDEVICE;
+    }
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete c;
+            return DGP_EDEVICE;
+        }
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return DGP_EDEVICE;
+    }
+    *out = c;
+    return DGP_OK;
+}
+
+dgp_status dgp_destroy(dgp_ctx *ctx) {
+    if (!ctx) return DGP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_mesh(ctx);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return DGP_OK;
+}
+
+dgp_status dgp_set_stream(dgp_ctx *ctx, void *hip_stream) {
+    if (!ctx) return DGP_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return DGP_OK;
+}
+
+const char *dgp_last_error(const dgp_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+
+dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
+    if (!ctx || !m) return DGP_EINVAL;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (m->dim != 2) return fail(ctx, DGP_EUNSUPPORTED, "dim %d: this version assembles 2D meshes", m->dim);
+    if (m->n_cells <= 0 || m->n_vertices <= 0 || m->n_faces <= 0)
+        return fail(ctx, DGP_EINVAL, "empty mesh (cells %lld, vertices %lld, faces %lld)", (long long)m->n_cells,
+                    (long long)m->n_vertices, (long long)m->n_faces);
+    if (m->n_cells > INT32_MAX / 2 || m->n_faces > INT32_MAX / 2 || m->n_vertices > INT32_MAX / 2)
+        return fail(ctx, DGP_EUNSUPPORTED, "mesh too large for 32-bit ids");
+    if (!m->x || !m->y || !m->cell_ptr || !m->cell_vtx || !m->cell_p || !m->cell_face_ptr || !m->cell_face ||
+        !m->face_vtx || !m->face_cell || !m->face_bc)
+        return fail(ctx, DGP_EINVAL, "null mesh array");
+    const int64_t N = m->n_cells, F = m->n_faces, V = m->n_vertices;
+    // ---- host validation: ids, loops, faces listed by the cells they bound
+    if (m->cell_ptr[0] != 0) return fail(ctx, DGP_EMESH, "cell_ptr[0] != 0");
+    int pmin = 99, pmax = -1;
+    for (int64_t c = 0; c < N; ++c) {
+        int64_t s = m->cell_ptr[c], e = m->cell_ptr[c + 1];
+        if (e - s < 3) return fail(ctx, DGP_EMESH, "cell %lld has %lld vertices", (long long)c, (long long)(e - s));
+        if (m->cell_face_ptr[c] != s || m->cell_face_ptr[c + 1] != e)
+            return fail(ctx, DGP_EMESH, "2D cell_face_ptr must equal cell_ptr (cell %lld)", (long long)c);
+        int p = m->cell_p[c];
+        if (p < 1 || p > kMaxP) return fail(ctx, DGP_EUNSUPPORTED, "cell %lld has degree %d", (long long)c, p);
+        pmin = p < pmin ? p : pmin;
+        pmax = p > pmax ? p : pmax;
+        for (int64_t k = s; k < e; ++k) {
+            int32_t v = m->cell_vtx[k], f = m->cell_face[k];
+            if (v < 0 || v >= V) return fail(ctx, DGP_EMESH, "cell %lld: vertex id %d out of range", (long long)c, v);
+            if (f < 0 || f >= F) return fail(ctx, DGP_EMESH, "cell %lld: face id %d out of range", (long long)c, f);
+            if (m->face_cell[2 * f] != c && m->face_cell[2 * f + 1] != c)
+                return fail(ctx, DGP_EMESH, "face %d is not adjacent to cell %lld", f, (long long)c);
+            int32_t w = m->cell_vtx[k + 1 < e ? k + 1 : s];
+            int32_t a = m->face_vtx[2 * f], b = m->face_vtx[2 * f + 1];
+            if (!((a == v && b == w) || (a == w && b == v)))
+                return fail(ctx, DGP_EMESH, "face %d does not match edge %lld of cell %lld", f, (long long)(k - s),
+                            (long long)c);
+        }
+    }
+    int64_t nnz_v = m->cell_ptr[N];
+    for (int64_t f = 0; f < F; ++f) {
+        int32_t l = m->face_cell[2 * f], r = m->face_cell[2 * f + 1];
+        int8_t bc = m->face_bc[f];
+        if (l < 0 || l >= N || r < -1 || r >= N || r == l)
+            return fail(ctx, DGP_EMESH, "face %lld: bad cells (%d, %d)", (long long)f, l, r);
+        if ((r < 0) != (bc != 0) || bc < 0 || bc > 2)
+            return fail(ctx, DGP_EMESH, "face %lld: boundary code %d inconsistent with cells", (long long)f, bc);
+        if (m->face_vtx[2 * f] >= m->face_vtx[2 * f + 1])
+            return fail(ctx, DGP_EMESH, "face %lld: vertices not in canonical (ascending) order", (long long)f);
+    }
+    free_mesh(ctx);
+    ctx->dim = 2;
+    ctx->n_cells = N;
+    ctx->n_faces = F;
+    ctx->n_vertices = V;
+    ctx->n_cell_vtx = nnz_v;
+    ctx->p_uniform = pmin == pmax ? pmin : -1;
+    DevMesh &d = ctx->dm;
+    d.n_cells = (int32_t)N;
+    d.n_faces = (int32_t)F;
+    d.n_vertices = (int32_t)V;
+    dgp_status st;
+#define UP(arr, n, field)                                         \
+    if ((st = upload(ctx, m->arr, (n), &d.field)) != DGP_OK) { \
+        free_mesh(ctx);                                           \
+        return st;                                                \
+    }
+    UP(x, V, x)
+    UP(y, V, y)
+    UP(cell_ptr, N + 1, cell_ptr)
+    UP(cell_vtx, nnz_v, cell_vtx)
+    UP(cell_p, N, cell_p)
+    UP(cell_face_ptr, N + 1, cell_face_ptr)
+    UP(cell_face, nnz_v, cell_face)
+    UP(face_vtx, 2 * F, face_vtx)
+    UP(face_cell, 2 * F, face_cell)
+    UP(face_bc, F, face_bc)
+#undef UP
+    int64_t n_tiles = (N + kTile - 1) / kTile;
+    if (hipMalloc(&ctx->tile_sums, sizeof(int64_t) * 3 * n_tiles) != hipSuccess ||
+        hipMalloc(&ctx->totals, sizeof(int64_t) * 4) != hipSuccess ||
+        hipMalloc(&ctx->geo, sizeof(CellGeo) * N) != hipSuccess) {
+        free_mesh(ctx);
+        return fail(ctx, DGP_ENOMEM, "device allocation failed");
+    }
+    ctx->has_mesh = true;
+    return DGP_OK;
+}
+
+static void launch_pattern_ctx(dgp_ctx *c, hipStream_t st) {
+    launch_pattern(c->dm, c->tile_sums, c->totals, c->row_ptr, c->col_idx, c->val_ptr, c->dof_ptr, st);
+}
+
+dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
+    if (!ctx || !out) return DGP_EINVAL;
+    if (!ctx->has_mesh) return fail(ctx, DGP_ESTATE, "dgp_pattern before dgp_mesh_upload");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    free_pattern(ctx);
+    free_graph(ctx);
+    // sizes: counts and scan only, read back once
+    launch_pattern(ctx->dm, ctx->tile_sums, ctx->totals, nullptr, nullptr, nullptr, nullptr, ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    int64_t tot[3];
+    HIPCHK(ctx, hipMemcpyAsync(tot, ctx->totals, sizeof(tot), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->nnzb = tot[0];
+    ctx->n_vals = tot[1];
+    ctx->n_dofs = tot[2];
+    if (hipMalloc(&ctx->row_ptr, sizeof(int64_t) * (ctx->n_cells + 1)) != hipSuccess ||
+        hipMalloc(&ctx->col_idx, sizeof(int32_t) * ctx->nnzb) != hipSuccess ||
+        hipMalloc(&ctx->val_ptr, sizeof(int64_t) * (ctx->nnzb + 1)) != hipSuccess ||
+        hipMalloc(&ctx->dof_ptr, sizeof(int64_t) * (ctx->n_cells + 1)) != hipSuccess) {
+        free_pattern(ctx);
+        return fail(ctx, DGP_ENOMEM, "pattern allocation failed");
+    }
+    launch_pattern_ctx(ctx, ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->has_pattern = true;
+    out->n_rows = ctx->n_cells;
+    out->nnzb = ctx->nnzb;
+    out->n_vals = ctx->n_vals;
+    out->n_dofs = ctx->n_dofs;
+    out->row_ptr = ctx->row_ptr;
+    out->col_idx = ctx->col_idx;
+    out->val_ptr = ctx->val_ptr;
+    out->dof_ptr = ctx->dof_ptr;
+    return DGP_OK;
+}
+
+dgp_status dgp_pattern_copy(dgp_ctx *ctx, int64_t *row_ptr, int32_t *col_idx, int64_t *val_ptr, int64_t *dof_ptr) {
+    if (!ctx) return DGP_EINVAL;
+    if (!ctx->has_pattern) return fail(ctx, DGP_ESTATE, "dgp_pattern_copy before dgp_pattern");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    if (row_ptr) HIPCHK(ctx, hipMemcpyAsync(row_ptr, ctx->row_ptr, 8 * (ctx->n_cells + 1), k, ctx->stream));
+    if (col_idx) HIPCHK(ctx, hipMemcpyAsync(col_idx, ctx->col_idx, 4 * ctx->nnzb, k, ctx->stream));
+    if (val_ptr) HIPCHK(ctx, hipMemcpyAsync(val_ptr, ctx->val_ptr, 8 * (ctx->nnzb + 1), k, ctx->stream));
+    if (dof_ptr) HIPCHK(ctx, hipMemcpyAsync(dof_ptr, ctx->dof_ptr, 8 * (ctx->n_cells + 1), k, ctx->stream));
+    return DGP_OK;
+}
+
+static DevProblem to_dev(const dgp_problem *p) {
+    DevProblem d;
+    d.a0 = p->a0;
+    d.a1 = p->a1;
+    d.bx = p->b[0];
+    d.by = p->b[1];
+    d.c = p->c;
+    d.c_sigma = p->c_sigma;
+    d.u_kind = p->u_kind;
+    for (int i = 0; i < 10; ++i) d.u[i] = p->u_poly[i];
+    return d;
+}
+
+static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs) {
+    if (!ctx || !prob || !vals || !rhs) return fail(ctx, DGP_EINVAL, "null argument");
+    if (!ctx->has_pattern) return fail(ctx, DGP_ESTATE, "assembly before dgp_pattern");
+    if (precision != DGP_F64 && precision != DGP_F32) return fail(ctx, DGP_EINVAL, "precision %d", precision);
+    if (prob->u_kind != DGP_U_SIN && prob->u_kind != DGP_U_POLY) return fail(ctx, DGP_EINVAL, "u_kind");
+    if (!(prob->c_sigma >= 0.0)) return fail(ctx, DGP_EINVAL, "c_sigma must be >= 0");
+    if (ctx->p_uniform < 1 || ctx->p_uniform > 3)
+        return fail(ctx, DGP_EUNSUPPORTED, "this version assembles meshes of one common degree p in 1..3");
+    return DGP_OK;
+}
+
+static dgp_status enqueue_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs,
+                                   hipStream_t st, bool with_pattern, bool timed) {
+    DevProblem dp = to_dev(prob);
+    if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
+    if (with_pattern) launch_pattern_ctx(ctx, st);
+    if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
+    launch_geometry(ctx->dm, dp, ctx->geo, st);
+    if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[2], st));
+    if (!launch_assemble2d(ctx->dm, dp, ctx->geo, ctx->row_ptr, ctx->col_idx, ctx->val_ptr, ctx->dof_ptr, precision,
+                           ctx->p_uniform, vals, rhs, st))
+        return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, ctx->p_uniform);
+    if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[3], st));
+    HIPCHK(ctx, hipGetLastError());
+    ctx->ev_pattern = timed && with_pattern;
+    ctx->ev_assemble = timed;
+    return DGP_OK;
+}
+
+dgp_status dgp_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs) {
+    dgp_status st = check_assemble_args(ctx, prob, precision, vals, rhs);
+    if (st) return st;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return enqueue_assemble(ctx, prob, precision, vals, rhs, ctx->stream, false, ctx->timing);
+}
+
+dgp_status dgp_run(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs) {
+    dgp_status st = check_assemble_args(ctx, prob, precision, vals, rhs);
+    if (st) return st;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return enqueue_assemble(ctx, prob, precision, vals, rhs, ctx->stream, true, ctx->timing);
+}
+
+dgp_status dgp_graph_capture(dgp_ctx *ctx, int what, const dgp_problem *prob, int precision, void *vals, void *rhs) {
+    dgp_status st = check_assemble_args(ctx, prob, precision, vals, rhs);
+    if (st) return st;
+    if (what != 0 && what != 1) return fail(ctx, DGP_EINVAL, "what = %d", what);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    free_graph(ctx);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    st = enqueue_assemble(ctx, prob, precision, vals, rhs, ctx->cap_stream, what == 0, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(ctx, DGP_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    ctx->graph = g;
+    e = hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        free_graph(ctx);
+        return fail(ctx, DGP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return DGP_OK;
+}
+
+dgp_status dgp_graph_launch(dgp_ctx *ctx) {
+    if (!ctx) return DGP_EINVAL;
+    if (!ctx->exec) return fail(ctx, DGP_ESTATE, "no captured graph");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipGraphLaunch(ctx->exec, ctx->stream));
+    return DGP_OK;
+}
+
+dgp_status dgp_set_timing(dgp_ctx *ctx, int enable) {
+    if (!ctx) return DGP_EINVAL;
+    ctx->timing = enable != 0;
+    return DGP_OK;
+}
+
+dgp_status dgp_kernel_ms(dgp_ctx *ctx, const char *name, float *ms) {
+    if (!ctx || !name || !ms) return DGP_EINVAL;
+    int a, b;
+    if (!strcmp(name, "pattern") && ctx->ev_pattern) {
+        a = 0;
+        b = 1;
+    } else if (!strcmp(name, "geometry") && ctx->ev_assemble) {
+        a = 1;
+        b = 2;
+    } else if (!strcmp(name, "assemble") && ctx->ev_assemble) {
+        a = 2;
+        b = 3;
+    } else {
+        return fail(ctx, DGP_ESTATE, "no timing recorded for '%s'", name);
+    }
+    HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
+    HIPCHK(ctx, hipEventElapsedTime(ms, ctx->ev[a], ctx->ev[b]));
+    return DGP_OK;
+}
+
+}  // extern "C"
