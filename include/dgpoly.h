@@ -122,8 +122,8 @@ dgp_status dgp_pattern_copy(dgp_ctx *ctx, int64_t *row_ptr, int32_t *col_idx, in
 
 /* Assemble values and right-hand side into caller-owned device buffers of the
  * chosen precision: vals[n_vals], rhs[n_dofs] (float or double).  Requires
- * dgp_pattern.  Asynchronous on the context stream; runs the geometry kernel
- * (bounding boxes, diameters, abar) and the assembly kernel. */
+ * dgp_pattern.  Asynchronous on the context stream; runs the preparation
+ * kernel (bounding boxes, diameters, abar) and the assembly kernel. */
 dgp_status dgp_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs);
 
 /* The whole path on the device: pattern (recomputed into the context's
@@ -138,7 +138,8 @@ dgp_status dgp_graph_launch(dgp_ctx *ctx);
 
 /* Per-kernel timing of the last dgp_run / dgp_assemble (device milliseconds,
  * from HIP events recorded on the context stream around each kernel when
- * timing is enabled).  names: "pattern", "geometry", "assemble". */
+ * timing is enabled).  names: "prep" (geometry, and the pattern in dgp_run),
+ * "assemble". */
 dgp_status dgp_set_timing(dgp_ctx *ctx, int enable);
 dgp_status dgp_kernel_ms(dgp_ctx *ctx, const char *name, float *ms);
 

@@ -9,6 +9,16 @@ namespace dgp {
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxP = 4;          // 2D kernels are built for p = 1..4
 constexpr int kTile = 256;        // cells per work-group in the pattern kernels
+constexpr int kMaxFaces2D = 24;   // faces per polygon handled by the preparation kernel
+
+// State of the single-pass (decoupled look-back) scan over tiles of elements.
+struct Lookback {
+    unsigned long long *counter;  // tickets, never reset while the mesh lives
+    unsigned long long *status;   // per tile: (epoch << 2) | 1 aggregate, | 2 inclusive prefix
+    int64_t *agg;                 // per tile: blocks, values, dofs
+    int64_t *incl;                // per tile: inclusive prefix of the same
+    int *error;                   // set if a look-back ever gives up
+};
 
 // Device copy of the mesh (structure of arrays, as uploaded).
 struct DevMesh {

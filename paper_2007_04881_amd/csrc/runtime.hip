@@ -28,14 +28,22 @@ struct dgp_ctx {
     std::vector<void *> mesh_bufs;
     DevMesh dm{};
 
-    // pattern
+    std::vector<int64_t> h_cell_ptr;  // loop offsets, for the assembly chunk partition
+
+    // pattern (col_idx / val_ptr sized by the upper bound n_cells + n_cell_vtx)
     bool has_pattern = false;
     int64_t nnzb = 0, n_vals = 0, n_dofs = 0;
     int64_t *row_ptr = nullptr, *val_ptr = nullptr, *dof_ptr = nullptr;
     int32_t *col_idx = nullptr;
-    int64_t *tile_sums = nullptr, *totals = nullptr;
+    Lookback lb{};
+    void *lb_mem = nullptr;
+    int n_tiles = 0;
 
     CellGeo *geo = nullptr;
+
+    // assembly chunk partitions per (precision, p)
+    int32_t *chunks[2][kMaxP + 1] = {};
+    int n_chunks[2][kMaxP + 1] = {};
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -62,10 +70,6 @@ static dgp_status fail(dgp_ctx *ctx, dgp_status st, const char *fmt, ...) {
     } while (0)
 
 static void free_pattern(dgp_ctx *c) {
-    for (void *p : {(void *)c->row_ptr, (void *)c->col_idx, (void *)c->val_ptr, (void *)c->dof_ptr})
-        if (p) (void)hipFree(p);
-    c->row_ptr = c->val_ptr = c->dof_ptr = nullptr;
-    c->col_idx = nullptr;
     c->has_pattern = false;
 }
 
@@ -79,10 +83,20 @@ static void free_graph(dgp_ctx *c) {
 static void free_mesh(dgp_ctx *c) {
     for (void *p : c->mesh_bufs) (void)hipFree(p);
     c->mesh_bufs.clear();
-    for (void *p : {(void *)c->tile_sums, (void *)c->totals, (void *)c->geo})
+    for (void *p : {(void *)c->row_ptr, (void *)c->col_idx, (void *)c->val_ptr, (void *)c->dof_ptr,
+                    (void *)c->geo, c->lb_mem})
         if (p) (void)hipFree(p);
-    c->tile_sums = c->totals = nullptr;
+    c->row_ptr = c->val_ptr = c->dof_ptr = nullptr;
+    c->col_idx = nullptr;
     c->geo = nullptr;
+    c->lb_mem = nullptr;
+    for (int q = 0; q < 2; ++q)
+        for (int p = 0; p <= kMaxP; ++p) {
+            if (c->chunks[q][p]) (void)hipFree(c->chunks[q][p]);
+            c->chunks[q][p] = nullptr;
+            c->n_chunks[q][p] = 0;
+        }
+    c->h_cell_ptr.clear();
     c->has_mesh = false;
     free_pattern(c);
     free_graph(c);
@@ -165,6 +179,9 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     for (int64_t c = 0; c < N; ++c) {
         int64_t s = m->cell_ptr[c], e = m->cell_ptr[c + 1];
         if (e - s < 3) return fail(ctx, DGP_EMESH, "cell %lld has %lld vertices", (long long)c, (long long)(e - s));
+        if (e - s > kMaxFaces2D)
+            return fail(ctx, DGP_EUNSUPPORTED, "cell %lld has %lld faces (at most %d)", (long long)c,
+                        (long long)(e - s), kMaxFaces2D);
         if (m->cell_face_ptr[c] != s || m->cell_face_ptr[c + 1] != e)
             return fail(ctx, DGP_EMESH, "2D cell_face_ptr must equal cell_ptr (cell %lld)", (long long)c);
         int p = m->cell_p[c];
@@ -223,19 +240,37 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     UP(face_cell, 2 * F, face_cell)
     UP(face_bc, F, face_bc)
 #undef UP
-    int64_t n_tiles = (N + kTile - 1) / kTile;
-    if (hipMalloc(&ctx->tile_sums, sizeof(int64_t) * 3 * n_tiles) != hipSuccess ||
-        hipMalloc(&ctx->totals, sizeof(int64_t) * 4) != hipSuccess ||
-        hipMalloc(&ctx->geo, sizeof(CellGeo) * N) != hipSuccess) {
+    // pattern arrays at their upper bound (a row has at most 1 + #faces blocks),
+    // geometry records and the look-back state of the single-pass scan
+    const int64_t nnzb_max = N + nnz_v;
+    ctx->n_tiles = prep_tiles((int)N);
+    const size_t T = (size_t)ctx->n_tiles;
+    const size_t lb_bytes = 8 /*counter*/ + 8 * T /*status*/ + 24 * T /*agg*/ + 24 * T /*incl*/ + 8 /*error*/;
+    if (hipMalloc(&ctx->row_ptr, sizeof(int64_t) * (N + 1)) != hipSuccess ||
+        hipMalloc(&ctx->col_idx, sizeof(int32_t) * nnzb_max) != hipSuccess ||
+        hipMalloc(&ctx->val_ptr, sizeof(int64_t) * (nnzb_max + 1)) != hipSuccess ||
+        hipMalloc(&ctx->dof_ptr, sizeof(int64_t) * (N + 1)) != hipSuccess ||
+        hipMalloc(&ctx->geo, sizeof(CellGeo) * N) != hipSuccess || hipMalloc(&ctx->lb_mem, lb_bytes) != hipSuccess) {
         free_mesh(ctx);
         return fail(ctx, DGP_ENOMEM, "device allocation failed");
     }
+    HIPCHK(ctx, hipMemset(ctx->lb_mem, 0, lb_bytes));
+    char *b = static_cast<char *>(ctx->lb_mem);
+    ctx->lb.counter = reinterpret_cast<unsigned long long *>(b);
+    ctx->lb.status = reinterpret_cast<unsigned long long *>(b + 8);
+    ctx->lb.agg = reinterpret_cast<int64_t *>(b + 8 + 8 * T);
+    ctx->lb.incl = reinterpret_cast<int64_t *>(b + 8 + 32 * T);
+    ctx->lb.error = reinterpret_cast<int *>(b + 8 + 56 * T);
+    ctx->h_cell_ptr.assign(m->cell_ptr, m->cell_ptr + N + 1);
     ctx->has_mesh = true;
     return DGP_OK;
 }
 
-static void launch_pattern_ctx(dgp_ctx *c, hipStream_t st) {
-    launch_pattern(c->dm, c->tile_sums, c->totals, c->row_ptr, c->col_idx, c->val_ptr, c->dof_ptr, st);
+static DevProblem neutral_problem() {
+    DevProblem d{};
+    d.a0 = 1.0;
+    d.c_sigma = 10.0;
+    return d;
 }
 
 dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
@@ -244,25 +279,19 @@ dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
     HIPCHK(ctx, hipSetDevice(ctx->device));
     free_pattern(ctx);
     free_graph(ctx);
-    // sizes: counts and scan only, read back once
-    launch_pattern(ctx->dm, ctx->tile_sums, ctx->totals, nullptr, nullptr, nullptr, nullptr, ctx->stream);
+    launch_prep(ctx->dm, neutral_problem(), ctx->geo, true, ctx->lb, ctx->row_ptr, ctx->col_idx, ctx->val_ptr,
+                ctx->dof_ptr, ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     int64_t tot[3];
-    HIPCHK(ctx, hipMemcpyAsync(tot, ctx->totals, sizeof(tot), hipMemcpyDeviceToHost, ctx->stream));
+    int err = 0;
+    HIPCHK(ctx, hipMemcpyAsync(tot, ctx->lb.incl + 3 * (ctx->n_tiles - 1), sizeof(tot), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(&err, ctx->lb.error, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (err) return fail(ctx, DGP_EDEVICE, "pattern scan look-back did not complete");
     ctx->nnzb = tot[0];
     ctx->n_vals = tot[1];
     ctx->n_dofs = tot[2];
-    if (hipMalloc(&ctx->row_ptr, sizeof(int64_t) * (ctx->n_cells + 1)) != hipSuccess ||
-        hipMalloc(&ctx->col_idx, sizeof(int32_t) * ctx->nnzb) != hipSuccess ||
-        hipMalloc(&ctx->val_ptr, sizeof(int64_t) * (ctx->nnzb + 1)) != hipSuccess ||
-        hipMalloc(&ctx->dof_ptr, sizeof(int64_t) * (ctx->n_cells + 1)) != hipSuccess) {
-        free_pattern(ctx);
-        return fail(ctx, DGP_ENOMEM, "pattern allocation failed");
-    }
-    launch_pattern_ctx(ctx, ctx->stream);
-    HIPCHK(ctx, hipGetLastError());
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->has_pattern = true;
     out->n_rows = ctx->n_cells;
     out->nnzb = ctx->nnzb;
@@ -300,6 +329,8 @@ static DevProblem to_dev(const dgp_problem *p) {
     return d;
 }
 
+static dgp_status prepare_chunks(dgp_ctx *ctx, int precision, int p);
+
 static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs) {
     if (!ctx || !prob || !vals || !rhs) return fail(ctx, DGP_EINVAL, "null argument");
     if (!ctx->has_pattern) return fail(ctx, DGP_ESTATE, "assembly before dgp_pattern");
@@ -308,23 +339,56 @@ static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int
     if (!(prob->c_sigma >= 0.0)) return fail(ctx, DGP_EINVAL, "c_sigma must be >= 0");
     if (ctx->p_uniform < 1 || ctx->p_uniform > 3)
         return fail(ctx, DGP_EUNSUPPORTED, "this version assembles meshes of one common degree p in 1..3");
+    return prepare_chunks(ctx, precision, ctx->p_uniform);
+}
+
+// Cut the rows into chunks of consecutive rows whose quadrature tasks, face
+// tasks, elements and (upper-bound) blocks fit one assembly work-group.
+static dgp_status prepare_chunks(dgp_ctx *ctx, int precision, int p) {
+    if (ctx->chunks[precision][p]) return DGP_OK;
+    AsmLimits lim;
+    assemble_limits(precision, p, &lim);
+    if (lim.slots == 0) return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
+    std::vector<int32_t> starts{0};
+    int tasks = 0, faces = 0, cells = 0, blocks = 0;
+    for (int64_t c = 0; c < ctx->n_cells; ++c) {
+        const int nv = (int)(ctx->h_cell_ptr[c + 1] - ctx->h_cell_ptr[c]);
+        const int t = (nv - 2) * lim.tasks_per_triangle + nv, b = nv + 1;
+        if (t > lim.slots || nv > lim.fslots || b > lim.maxb)
+            return fail(ctx, DGP_EUNSUPPORTED, "cell %lld is too large for one work-group", (long long)c);
+        if (tasks + t > lim.slots || faces + nv > lim.fslots || cells + 1 > lim.maxc || blocks + b > lim.maxb) {
+            starts.push_back((int32_t)c);
+            tasks = faces = cells = blocks = 0;
+        }
+        tasks += t;
+        faces += nv;
+        cells += 1;
+        blocks += b;
+    }
+    starts.push_back((int32_t)ctx->n_cells);
+    int32_t *d = nullptr;
+    if (hipMalloc(&d, sizeof(int32_t) * starts.size()) != hipSuccess)
+        return fail(ctx, DGP_ENOMEM, "chunk table allocation failed");
+    HIPCHK(ctx, hipMemcpy(d, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice));
+    ctx->chunks[precision][p] = d;
+    ctx->n_chunks[precision][p] = (int)starts.size() - 1;
     return DGP_OK;
 }
 
 static dgp_status enqueue_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs,
                                    hipStream_t st, bool with_pattern, bool timed) {
     DevProblem dp = to_dev(prob);
+    const int p = ctx->p_uniform;
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
-    if (with_pattern) launch_pattern_ctx(ctx, st);
+    launch_prep(ctx->dm, dp, ctx->geo, with_pattern, ctx->lb, ctx->row_ptr, ctx->col_idx, ctx->val_ptr,
+                ctx->dof_ptr, st);
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
-    launch_geometry(ctx->dm, dp, ctx->geo, st);
+    if (!launch_assemble2d(ctx->dm, dp, ctx->geo, ctx->row_ptr, ctx->col_idx, ctx->val_ptr, ctx->dof_ptr,
+                           ctx->chunks[precision][p], ctx->n_chunks[precision][p], precision, p, vals, rhs, st))
+        return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[2], st));
-    if (!launch_assemble2d(ctx->dm, dp, ctx->geo, ctx->row_ptr, ctx->col_idx, ctx->val_ptr, ctx->dof_ptr, precision,
-                           ctx->p_uniform, vals, rhs, st))
-        return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, ctx->p_uniform);
-    if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[3], st));
     HIPCHK(ctx, hipGetLastError());
-    ctx->ev_pattern = timed && with_pattern;
+    ctx->ev_pattern = timed;
     ctx->ev_assemble = timed;
     return DGP_OK;
 }
@@ -385,19 +449,16 @@ dgp_status dgp_set_timing(dgp_ctx *ctx, int enable) {
 dgp_status dgp_kernel_ms(dgp_ctx *ctx, const char *name, float *ms) {
     if (!ctx || !name || !ms) return DGP_EINVAL;
     int a, b;
-    if (!strcmp(name, "pattern") && ctx->ev_pattern) {
+    if (!strcmp(name, "prep") && ctx->ev_pattern) {
         a = 0;
         b = 1;
-    } else if (!strcmp(name, "geometry") && ctx->ev_assemble) {
+    } else if (!strcmp(name, "assemble") && ctx->ev_assemble) {
         a = 1;
         b = 2;
-    } else if (!strcmp(name, "assemble") && ctx->ev_assemble) {
-        a = 2;
-        b = 3;
     } else {
         return fail(ctx, DGP_ESTATE, "no timing recorded for '%s'", name);
     }
-    HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
+    HIPCHK(ctx, hipEventSynchronize(ctx->ev[2]));
     HIPCHK(ctx, hipEventElapsedTime(ms, ctx->ev[a], ctx->ev[b]));
     return DGP_OK;
 }
