@@ -183,6 +183,32 @@ def backward(params, X, M, area):
     return grads
 
 
+def flatten(params):
+    """Parameter blob: W1, b1, W2, b2, W3, b3, W4, b4, each row-major ([in][out] for weights)."""
+    return np.concatenate([p.ravel() for p in params])
+
+
+def unflatten(blob):
+    dims = [NIN, NHID, NHID, NHID, NOUT]
+    out, o = [], 0
+    for i in range(4):
+        n = dims[i] * dims[i + 1]
+        out.append(np.asarray(blob[o:o + n], dtype=np.float64).reshape(dims[i], dims[i + 1]))
+        o += n
+        out.append(np.asarray(blob[o:o + dims[i + 1]], dtype=np.float64))
+        o += dims[i + 1]
+    return out
+
+
+def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma and Ba, ICLR 2015) with bias correction; returns new (p, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
 # ---------------------------------------------------------------- refinement
 def jacobian(nodes, w):
     """J [28, 48] of Q with respect to (xi_1, eta_1, ..., xi_16, eta_16, w_1..w_16)."""
@@ -208,6 +234,43 @@ def gauss_newton(nodes, w, M, iters=4, lam=1e-12):
         nodes = nodes + du[:2 * NNODE].reshape(NNODE, 2)
         w = w + du[2 * NNODE:]
     return nodes, w
+
+
+def levenberg_marquardt(nodes, w, M, area, max_it=8, tol=1e-10, mu0=1e-6):
+    """Damped minimum-norm Gauss-Newton (Levenberg-Marquardt) on the moment equations.
+
+    Step du = -J^T (J J^T + mu g I)^{-1} r with g = max diag(J J^T); a step is
+    taken only if it lowers ||r||_2 (then mu /= 10, floor 1e-15), otherwise mu
+    is multiplied by 10 and the step recomputed (giving up above mu = 1e6).
+    Stops when max|r| / area <= tol (accepted) or after max_it steps.
+    Returns nodes, weights, steps taken, accepted."""
+    u = np.concatenate([nodes.ravel(), w])
+    res = lambda u: rule_moments(u[:2 * NNODE].reshape(NNODE, 2), u[2 * NNODE:]) - M
+    r = res(u)
+    mu = mu0
+    it = 0
+    while True:
+        if np.max(np.abs(r)) / abs(area) <= tol:
+            return u[:2 * NNODE].reshape(NNODE, 2), u[2 * NNODE:], it, True
+        if it >= max_it:
+            break
+        J = jacobian(u[:2 * NNODE].reshape(NNODE, 2), u[2 * NNODE:])
+        G = J @ J.T
+        g = np.max(np.diag(G))
+        taken = False
+        while mu <= 1e6:
+            du = -J.T @ np.linalg.solve(G + mu * g * np.eye(NMOM), r)
+            rt = res(u + du)
+            if rt @ rt < r @ r:
+                u, r = u + du, rt
+                mu = max(mu / 10.0, 1e-15)
+                taken = True
+                break
+            mu *= 10.0
+        if not taken:
+            break
+        it += 1
+    return u[:2 * NNODE].reshape(NNODE, 2), u[2 * NNODE:], it, False
 
 
 def template_rule(area):

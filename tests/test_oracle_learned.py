@@ -211,3 +211,44 @@ def test_training_polygons_recipe():
     assert counts[:3].sum() == 0 and np.all(counts[3:] > 10)
     # reproducible per index, independent of the order of generation
     assert np.array_equal(L.random_polygon(77, SEED), L.random_polygon(77, SEED))
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    """With zero moments, the bias-corrected first step is lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal(50)
+    p0 = rng.standard_normal(50)
+    p1, m, v = L.adam_step(p0, g, np.zeros(50), np.zeros(50), 1, lr=0.01, eps=0.0)
+    assert np.allclose(p0 - p1, 0.01 * np.sign(g), rtol=1e-12, atol=0)
+    # a constant gradient keeps the step at lr (the corrections cancel the moment decay)
+    for t in range(2, 6):
+        p1, m, v = L.adam_step(p1, g, m, v, t, lr=0.01, eps=0.0)
+    assert np.allclose(p0 - p1, 0.05 * np.sign(g), rtol=1e-10, atol=0)
+
+
+def test_blob_round_trip():
+    params = L.init_params(4)
+    blob = L.flatten(params)
+    assert blob.size == 43952
+    back = L.unflatten(blob)
+    assert all(np.array_equal(a, b) for a, b in zip(params, back))
+
+
+def test_levenberg_marquardt_accepts_from_template_and_perturbed_square():
+    for index in (1, 4, 13):
+        v = L.random_polygon(index, SEED)
+        A = L.polygon_area(v)
+        M = L.polygon_moments(v)
+        n, w = L.template_rule(A)
+        n, w, it, ok = L.levenberg_marquardt(n, w, M, A, max_it=10)
+        assert ok and 1 <= it <= 10
+        assert L.residual(n, w, M, A) <= 1e-10
+    sq = np.array([[-1.0, -1.0], [1.0, -1.0], [1.0, 1.0], [-1.0, 1.0]])
+    M = L.polygon_moments(sq)
+    n, w = L.template_rule(4.0)
+    _, _, it, ok = L.levenberg_marquardt(n, w, M, 4.0)
+    assert ok and it == 0  # the Gauss tensor rule is already exact
+    rng = np.random.default_rng(11)
+    n2 = n + 0.3 * rng.standard_normal(n.shape)  # far from any rule: plain steps overshoot
+    n2, w2, it, ok = L.levenberg_marquardt(n2, w * 1.5, M, 4.0, max_it=40)
+    assert ok and L.residual(n2, w2, M, 4.0) <= 1e-10
