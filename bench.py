@@ -24,6 +24,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes(mesh, info, val_bytes):
     """Bytes the assembly kernel must move at least once: mesh connectivity and
     coordinates, per-cell geometry records, the pattern it reads, and the values
@@ -55,12 +59,88 @@ def cpu_baseline(mesh, params, budget_s=12.0):
                 elements_per_s=mesh.n_cells * reps / t_total)
 
 
+TRAIN_SEED = 2007048815  # key of the training polygon stream
+
+
+def _replay_ms(ctx, D, torch, steps, warmup):
+    for _ in range(warmup):
+        ctx.graph_launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.graph_launch()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def reduced_rule_study(D, torch, steps, warmup, train_polygons, train_epochs):
+    """Reduced volume rules on the 262,144-cell Voronoi mesh at p = 3 (Poisson):
+    network training, rule construction from the network and from the untrained
+    4 x 4 Gauss template, and the assembly with plain and with reduced rules."""
+    from meshgen import config_mesh, problem_params
+    log("reduced rules: 262,144-cell mesh")
+    mesh = config_mesh(5)
+    params = problem_params(5)
+    ctx = D.Context(0)
+    ctx.upload(mesh)
+    info = ctx.pattern()
+    log(f"training on {train_polygons} polygons, {train_epochs} epochs")
+    t0 = time.perf_counter()
+    _, losses, tst = ctx.mlp_train(train_polygons, TRAIN_SEED, init_seed=1, epochs=train_epochs, batch=4096,
+                                   lr=2e-3)
+    train_s = time.perf_counter() - t0
+
+    def build(init):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = ctx.qrule_build(init, 8, 1e-10)
+        ms = (time.perf_counter() - t) * 1e3
+        n_acc = max(st.n_accepted, 1)
+        mean_it = sum(k * st.iters_hist[k] for k in range(16)) / n_acc
+        return dict(wall_ms=ms, features_ms=st.ms_features, network_ms=st.ms_network, refine_ms=st.ms_refine,
+                    eligible=st.n_eligible, accepted=st.n_accepted, accepted_frac=st.n_accepted / max(st.n_eligible, 1),
+                    mean_steps=mean_it, steps_hist=list(st.iters_hist), max_residual=st.max_residual_accepted)
+
+    log(f"trained in {time.perf_counter() - t0:.1f} s; building rules")
+    tmpl = build(D.INIT_TEMPLATE)
+    net = build(D.INIT_NETWORK)
+    log("timing plain and reduced assembly")
+    vals, rhs = ctx.outputs(D.F32)
+    t = {}
+    kern = {}
+    for mode, name in ((D.RULE_PLAIN, "plain"), (D.RULE_REDUCED, "reduced")):
+        ctx.graph_capture(1, params, D.F32, vals, rhs, rule_mode=mode)
+        t[name] = _replay_ms(ctx, D, torch, steps, warmup)
+        ctx.set_timing(True)
+        ks = []
+        for _ in range(10):
+            ctx.assemble(params, D.F32, vals, rhs, rule_mode=mode)
+            ks.append(ctx.kernel_ms("assemble"))
+        ctx.set_timing(False)
+        kern[name] = sorted(ks)[len(ks) // 2]
+    gain = kern["plain"] - kern["reduced"]
+    rulegen = net["features_ms"] + net["network_ms"] + net["refine_ms"]
+    ctx.close()
+    return {"workload": "262144-cell seeded Voronoi, p=3, Poisson, FP32 assembly",
+            "cells": mesh.n_cells, "nnzb": info.nnzb,
+            "training": {"polygons": train_polygons, "epochs": train_epochs, "steps": tst.steps, "seconds": train_s,
+                         "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])},
+            "rules_network_init": net, "rules_template_init": tmpl,
+            "assemble_ms": t, "assemble_kernel_ms": kern,
+            "kernel_speedup": kern["plain"] / kern["reduced"],
+            "rulegen_ms": rulegen,
+            "break_even_assemblies": (rulegen / gain) if gain > 0 else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-rule study")
+    ap.add_argument("--train-polygons", type=int, default=1_000_000)
+    ap.add_argument("--train-epochs", type=int, default=30)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -72,6 +152,7 @@ def main():
     import paper_2007_04881_amd as D
     from meshgen import config_mesh, problem_params
 
+    log("16,384-cell mesh")
     mesh = config_mesh(2)
     params = problem_params(2)
     ctx = D.Context(0)
@@ -145,9 +226,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_assemble2d<float,2>", "algorithmic_bytes": abytes},
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(mesh, params)
     ctx.close()
+    if not args.no_reduced:
+        out["reduced_rules"] = reduced_rule_study(D, torch, 20, 3, args.train_polygons, args.train_epochs)
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(mesh, params)
     print(json.dumps(out))
 
 

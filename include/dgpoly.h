@@ -52,6 +52,14 @@ typedef int32_t dgp_status;
 #define DGP_F64 0 /* contraction and output in double precision */
 #define DGP_F32 1 /* geometry, penalty and weights in FP64; contraction and output in FP32 */
 
+#define DGP_RULE_PLAIN 0   /* volume terms on the fan sub-triangles (Section 3) */
+#define DGP_RULE_REDUCED 1 /* volume matrix with each element's accepted 16-node rule (dgp_qrule_build) */
+
+#define DGP_INIT_NETWORK 0  /* reduced rules start from the network's prediction */
+#define DGP_INIT_TEMPLATE 1 /* reduced rules start from the 4 x 4 Gauss tensor rule on the box */
+
+#define DGP_MLP_PARAMS 43952 /* FP32 parameters of the rule network */
+
 #define DGP_U_SIN 0  /* manufactured u = sin(pi x) sin(pi y) */
 #define DGP_U_POLY 1 /* u = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 y^2 + c6 z^2 + c7 xy + c8 xz + c9 yz */
 
@@ -123,17 +131,25 @@ dgp_status dgp_pattern_copy(dgp_ctx *ctx, int64_t *row_ptr, int32_t *col_idx, in
 /* Assemble values and right-hand side into caller-owned device buffers of the
  * chosen precision: vals[n_vals], rhs[n_dofs] (float or double).  Requires
  * dgp_pattern.  Asynchronous on the context stream; runs the preparation
- * kernel (bounding boxes, diameters, abar) and the assembly kernel. */
-dgp_status dgp_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs);
+ * kernel (bounding boxes, diameters, abar) and the assembly kernel, which
+ * leaves the pattern arrays untouched.
+ * rule_mode DGP_RULE_REDUCED integrates the volume matrix of every element
+ * whose reduced rule was accepted by dgp_qrule_build with that rule, and the
+ * rest as DGP_RULE_PLAIN; the load vector and the faces always use the plain
+ * rules.  It needs constant coefficients (a1 = 0) and p <= 3, so that every
+ * volume integrand has degree <= 6 (DGP_EINVAL / DGP_EUNSUPPORTED otherwise),
+ * and a prior dgp_qrule_build (DGP_ESTATE). */
+dgp_status dgp_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode, void *vals, void *rhs);
 
 /* The whole path on the device: pattern (recomputed into the context's
  * arrays, bit-identical), geometry, assembly.  Requires a prior dgp_pattern
  * (sizes known).  Asynchronous; no host synchronisation. */
-dgp_status dgp_run(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs);
+dgp_status dgp_run(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode, void *vals, void *rhs);
 
 /* Capture dgp_run (what = 0) or dgp_assemble (what = 1) with these arguments
  * into a HIP graph held by the context, and replay it. */
-dgp_status dgp_graph_capture(dgp_ctx *ctx, int what, const dgp_problem *prob, int precision, void *vals, void *rhs);
+dgp_status dgp_graph_capture(dgp_ctx *ctx, int what, const dgp_problem *prob, int precision, int rule_mode,
+                             void *vals, void *rhs);
 dgp_status dgp_graph_launch(dgp_ctx *ctx);
 
 /* Per-kernel timing of the last dgp_run / dgp_assemble (device milliseconds,
@@ -142,6 +158,98 @@ dgp_status dgp_graph_launch(dgp_ctx *ctx);
  * "assemble". */
 dgp_status dgp_set_timing(dgp_ctx *ctx, int enable);
 dgp_status dgp_kernel_ms(dgp_ctx *ctx, const char *name, float *ms);
+
+/* ---------------------------------------------------------------------
+ * Reduced volume rules for polygons (an extension of Section 3: the paper
+ * integrates on the fan sub-triangles only).  Every element with at most 12
+ * vertices is mapped to [-1, 1]^2 by its bounding box; a network predicts a
+ * 16-node rule (nodes in [-1, 1]^2, weights summing to the mapped area |P|),
+ * FP64 damped minimum-norm Gauss-Newton steps (Levenberg-Marquardt: a step
+ * du = -J^T (J J^T + mu g I)^{-1} r, g = max diag(J J^T), is taken only if it
+ * lowers ||r||_2, mu starting at 1e-6) fit it to the element's 28 Legendre
+ * moments int_P P_a(xi) P_b(eta), a + b <= 6, and the rule is accepted iff
+ * max_ab |Q_ab - M_ab| / |P| <= tol.  Network: 36 inputs (the loop's 12
+ * vertices from the one of smallest xi, then eta, zero padded, and 12 validity
+ * flags), three SiLU layers of 128, 48 outputs (nodes tanh(z_0..31) as
+ * (xi, eta) pairs, weights |P| softmax(z_32..47)).  Parameter blob (FP32,
+ * weights [in][out] row-major): W1[36][128] b1[128] W2[128][128] b2 W3[128][128]
+ * b3 W4[128][48] b4[48]. */
+typedef struct {
+    int64_t n_cells, n_eligible, n_accepted;
+    int64_t iters_hist[16];      /* accepted elements by refinement steps taken (15 = 15 or more) */
+    double max_residual_accepted;
+    float ms_features, ms_network, ms_refine; /* device time of the three stages */
+} dgp_qrule_stats;
+
+typedef struct {
+    int64_t n_polygons;          /* training polygons, indices 0 .. n-1 of the seeded stream */
+    uint64_t data_seed;          /* key of the polygon stream (dgp_train_polygons) */
+    uint64_t init_seed;          /* initial weights N(0, 1/fan_in), biases 0 */
+    int32_t epochs, batch;
+    float lr, beta1, beta2, eps; /* Adam */
+} dgp_train_cfg;
+
+typedef struct {
+    float loss_first, loss_last; /* mean loss over the first and the last epoch */
+    double ms;                   /* wall time of data generation and training */
+    int64_t steps;
+} dgp_train_stats;
+
+/* Load network parameters from host memory (n_params = DGP_MLP_PARAMS). Synchronous. */
+dgp_status dgp_mlp_load(dgp_ctx *ctx, const float *params, int64_t n_params);
+
+/* Build a rule for every element of the uploaded mesh (requires dgp_pattern):
+ * element data, initial rule (init = DGP_INIT_NETWORK needs loaded or trained
+ * parameters), at most max_iters damped Gauss-Newton steps (stopping at tol), the
+ * acceptance flags.  Synchronous; fills *out if non-NULL. */
+dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dgp_qrule_stats *out);
+
+/* Copy the rules into caller-owned device buffers (any may be NULL):
+ * nodes[n_cells][16][2] (xi, eta), weights[n_cells][16], accepted[n_cells],
+ * residual[n_cells] (infinite for elements with more than 12 vertices),
+ * iters[n_cells].  Asynchronous. */
+dgp_status dgp_qrule_get(dgp_ctx *ctx, double *nodes, double *weights, uint8_t *accepted, double *residual,
+                         int32_t *iters);
+
+/* The element data behind the rules: features[n_cells][36] (float),
+ * moments[n_cells][28], area[n_cells] (|P| in box coordinates).  Asynchronous. */
+dgp_status dgp_qrule_cell_data(dgp_ctx *ctx, float *features, double *moments, double *area);
+
+/* Training polygons first .. first+n-1 (device buffers): features[n][36]
+ * (float), features64[n][36] (double, may be NULL), moments[n][28], area[n].
+ * Polygon i: Philox-4x32-10 keyed by (seed low word, seed high word), counter
+ * (i, j, 0, 0) for draw j; draw 0 fixes the vertex count 3 + floor(10 u0), the
+ * kind (convex if u1 < 1/2, else star-shaped), the aspect 0.3 + 0.7 u2 and the
+ * rotation 2 pi u3; draw j >= 1 places vertex j-1 at the angle
+ * 2 pi (j-1 + 0.1 + 0.8 u0) / m + rotation, on the ellipse (cos, aspect sin)
+ * or at radius 0.35 + 0.65 u1; u = (word >> 8) / 2^24.  The polygon is then
+ * normalised to its bounding box and rotated as for the elements.
+ * Asynchronous. */
+dgp_status dgp_train_polygons(dgp_ctx *ctx, uint64_t seed, int64_t first, int64_t n, float *features,
+                              double *features64, double *moments, double *area);
+
+/* Network output out[n][48] for rows x[n][36]; params, x, out are device
+ * pointers.  Synchronous (scratch is allocated and freed inside). */
+dgp_status dgp_mlp_forward(dgp_ctx *ctx, const float *params, const float *x, int64_t n, float *out);
+
+/* Gradient of the training loss, mean over the n rows of
+ * sum_ab (Q_ab - M_ab)^2 / |P|^2, with respect to every parameter
+ * (grad[DGP_MLP_PARAMS], blob layout), and the sum of the per-row losses into
+ * loss_sum[0].  Device pointers.  Synchronous. */
+dgp_status dgp_mlp_loss_grad(dgp_ctx *ctx, const float *params, const float *x, const double *moments,
+                             const double *area, int64_t n, float *grad, float *loss_sum);
+
+/* One Adam step (Kingma and Ba) on device arrays of n parameters, step t >= 1. */
+dgp_status dgp_adam_step(dgp_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n, int32_t t,
+                         float lr, float beta1, float beta2, float eps);
+
+/* Generate cfg->n_polygons training polygons on the device and train the
+ * network with Adam on mini-batches in index order; the result becomes the
+ * context's network and is copied to params_out (host, DGP_MLP_PARAMS floats,
+ * may be NULL); epoch_loss[epochs] (host, may be NULL) receives the mean loss
+ * of each epoch.  Synchronous. */
+dgp_status dgp_mlp_train(dgp_ctx *ctx, const dgp_train_cfg *cfg, float *params_out, float *epoch_loss,
+                         dgp_train_stats *stats);
 
 #ifdef __cplusplus
 }

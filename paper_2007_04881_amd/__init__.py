@@ -16,6 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libdgpoly.so")
 
 F64, F32 = 0, 1
 U_SIN, U_POLY = 0, 1
+RULE_PLAIN, RULE_REDUCED = 0, 1
+INIT_NETWORK, INIT_TEMPLATE = 0, 1
+MLP_PARAMS = 43952
 
 _STATUS = {0: "DGP_OK", -1: "DGP_EINVAL", -2: "DGP_EMESH", -3: "DGP_EUNSUPPORTED", -4: "DGP_ENOMEM",
            -5: "DGP_EDEVICE", -6: "DGP_ESTATE"}
@@ -47,9 +50,27 @@ class PatternInfo(C.Structure):
                 ("dof_ptr", C.c_void_p)]
 
 
+class QruleStats(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_eligible", C.c_int64), ("n_accepted", C.c_int64),
+                ("iters_hist", C.c_int64 * 16), ("max_residual_accepted", C.c_double),
+                ("ms_features", C.c_float), ("ms_network", C.c_float), ("ms_refine", C.c_float)]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("n_polygons", C.c_int64), ("data_seed", C.c_uint64), ("init_seed", C.c_uint64),
+                ("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [("loss_first", C.c_float), ("loss_last", C.c_float), ("ms", C.c_double), ("steps", C.c_int64)]
+
+
 EXPORTS = ["dgp_create", "dgp_destroy", "dgp_set_stream", "dgp_last_error", "dgp_mesh_upload", "dgp_pattern",
            "dgp_pattern_copy", "dgp_assemble", "dgp_run", "dgp_graph_capture", "dgp_graph_launch",
-           "dgp_set_timing", "dgp_kernel_ms"]
+           "dgp_set_timing", "dgp_kernel_ms", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
+           "dgp_qrule_cell_data", "dgp_train_polygons", "dgp_mlp_forward", "dgp_mlp_loss_grad", "dgp_adam_step",
+           "dgp_mlp_train"]
 
 _lib = None
 
@@ -74,9 +95,21 @@ def lib():
         L.dgp_pattern.argtypes = [C.c_void_p, C.POINTER(PatternInfo)]
         L.dgp_pattern_copy.argtypes = [C.c_void_p] + [C.c_void_p] * 4
         for name in ("dgp_assemble", "dgp_run"):
-            getattr(L, name).argtypes = [C.c_void_p, C.POINTER(ProblemDesc), C.c_int, C.c_void_p, C.c_void_p]
-        L.dgp_graph_capture.argtypes = [C.c_void_p, C.c_int, C.POINTER(ProblemDesc), C.c_int, C.c_void_p,
-                                        C.c_void_p]
+            getattr(L, name).argtypes = [C.c_void_p, C.POINTER(ProblemDesc), C.c_int, C.c_int, C.c_void_p,
+                                         C.c_void_p]
+        L.dgp_graph_capture.argtypes = [C.c_void_p, C.c_int, C.POINTER(ProblemDesc), C.c_int, C.c_int,
+                                        C.c_void_p, C.c_void_p]
+        L.dgp_mlp_load.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+        L.dgp_qrule_build.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.POINTER(QruleStats)]
+        L.dgp_qrule_get.argtypes = [C.c_void_p] + [C.c_void_p] * 5
+        L.dgp_qrule_cell_data.argtypes = [C.c_void_p] + [C.c_void_p] * 3
+        L.dgp_train_polygons.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, C.c_int64] + [C.c_void_p] * 4
+        L.dgp_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.dgp_mlp_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                        C.c_void_p, C.c_void_p]
+        L.dgp_adam_step.argtypes = [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int64, C.c_int32] + [C.c_float] * 4
+        L.dgp_mlp_train.argtypes = [C.c_void_p, C.POINTER(TrainCfg), C.c_void_p, C.c_void_p,
+                                    C.POINTER(TrainStats)]
         L.dgp_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.dgp_kernel_ms.argtypes = [C.c_void_p, C.c_char_p, C.POINTER(C.c_float)]
         _lib = L
@@ -189,22 +222,23 @@ class Context:
             if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
                 raise ValueError(f"outputs must be contiguous {dt} device tensors")
 
-    def assemble(self, problem: dict, precision, vals, rhs):
+    def assemble(self, problem: dict, precision, vals, rhs, rule_mode=RULE_PLAIN):
         self._tensors_ok(vals, rhs, precision)
         pd = problem_desc(problem)
-        self._check(lib().dgp_assemble(self._h, C.byref(pd), precision, vals.data_ptr(), rhs.data_ptr()),
+        self._check(lib().dgp_assemble(self._h, C.byref(pd), precision, rule_mode, vals.data_ptr(), rhs.data_ptr()),
                     "dgp_assemble")
 
-    def run(self, problem: dict, precision, vals, rhs):
+    def run(self, problem: dict, precision, vals, rhs, rule_mode=RULE_PLAIN):
         self._tensors_ok(vals, rhs, precision)
         pd = problem_desc(problem)
-        self._check(lib().dgp_run(self._h, C.byref(pd), precision, vals.data_ptr(), rhs.data_ptr()), "dgp_run")
+        self._check(lib().dgp_run(self._h, C.byref(pd), precision, rule_mode, vals.data_ptr(), rhs.data_ptr()),
+                    "dgp_run")
 
-    def graph_capture(self, what, problem: dict, precision, vals, rhs):
+    def graph_capture(self, what, problem: dict, precision, vals, rhs, rule_mode=RULE_PLAIN):
         self._tensors_ok(vals, rhs, precision)
         pd = problem_desc(problem)
-        self._check(lib().dgp_graph_capture(self._h, what, C.byref(pd), precision, vals.data_ptr(), rhs.data_ptr()),
-                    "dgp_graph_capture")
+        self._check(lib().dgp_graph_capture(self._h, what, C.byref(pd), precision, rule_mode, vals.data_ptr(),
+                                            rhs.data_ptr()), "dgp_graph_capture")
 
     def graph_launch(self):
         self._check(lib().dgp_graph_launch(self._h), "dgp_graph_launch")
@@ -216,3 +250,80 @@ class Context:
         ms = C.c_float()
         self._check(lib().dgp_kernel_ms(self._h, name.encode(), C.byref(ms)), "dgp_kernel_ms")
         return ms.value
+
+    # ------------------------------------------------------ reduced volume rules
+    def mlp_load(self, params):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(lib().dgp_mlp_load(self._h, a.ctypes.data, a.size), "dgp_mlp_load")
+
+    def qrule_build(self, init=INIT_NETWORK, max_iters=8, tol=1e-10) -> QruleStats:
+        st = QruleStats()
+        self._check(lib().dgp_qrule_build(self._h, init, max_iters, tol, C.byref(st)), "dgp_qrule_build")
+        return st
+
+    def qrule_get(self):
+        """nodes [N,16,2], weights [N,16], accepted [N] (uint8), residual [N], iters [N] as device tensors."""
+        import torch
+        n = self.info.n_rows
+        dev = torch.device("cuda", self.device)
+        nodes = torch.empty((n, 16, 2), dtype=torch.float64, device=dev)
+        w = torch.empty((n, 16), dtype=torch.float64, device=dev)
+        ok = torch.empty(n, dtype=torch.uint8, device=dev)
+        res = torch.empty(n, dtype=torch.float64, device=dev)
+        it = torch.empty(n, dtype=torch.int32, device=dev)
+        self._check(lib().dgp_qrule_get(self._h, nodes.data_ptr(), w.data_ptr(), ok.data_ptr(), res.data_ptr(),
+                                        it.data_ptr()), "dgp_qrule_get")
+        return nodes, w, ok, res, it
+
+    def qrule_cell_data(self):
+        import torch
+        n = self.info.n_rows
+        dev = torch.device("cuda", self.device)
+        feat = torch.empty((n, 36), dtype=torch.float32, device=dev)
+        mom = torch.empty((n, 28), dtype=torch.float64, device=dev)
+        area = torch.empty(n, dtype=torch.float64, device=dev)
+        self._check(lib().dgp_qrule_cell_data(self._h, feat.data_ptr(), mom.data_ptr(), area.data_ptr()),
+                    "dgp_qrule_cell_data")
+        return feat, mom, area
+
+    def train_polygons(self, seed, first, n, with_f64=False):
+        import torch
+        dev = torch.device("cuda", self.device)
+        feat = torch.empty((n, 36), dtype=torch.float32, device=dev)
+        f64 = torch.empty((n, 36), dtype=torch.float64, device=dev) if with_f64 else None
+        mom = torch.empty((n, 28), dtype=torch.float64, device=dev)
+        area = torch.empty(n, dtype=torch.float64, device=dev)
+        self._check(lib().dgp_train_polygons(self._h, seed, first, n, feat.data_ptr(),
+                                             f64.data_ptr() if f64 is not None else None, mom.data_ptr(),
+                                             area.data_ptr()), "dgp_train_polygons")
+        return feat, f64, mom, area
+
+    def mlp_forward(self, params, x):
+        import torch
+        out = torch.empty((x.shape[0], 48), dtype=torch.float32, device=x.device)
+        self._check(lib().dgp_mlp_forward(self._h, params.data_ptr(), x.data_ptr(), x.shape[0], out.data_ptr()),
+                    "dgp_mlp_forward")
+        return out
+
+    def mlp_loss_grad(self, params, x, moments, area):
+        import torch
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        self._check(lib().dgp_mlp_loss_grad(self._h, params.data_ptr(), x.data_ptr(), moments.data_ptr(),
+                                            area.data_ptr(), x.shape[0], g.data_ptr(), loss.data_ptr()),
+                    "dgp_mlp_loss_grad")
+        return g, loss
+
+    def adam_step(self, params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(lib().dgp_adam_step(self._h, params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                        params.numel(), t, lr, beta1, beta2, eps), "dgp_adam_step")
+
+    def mlp_train(self, n_polygons, data_seed, init_seed=1, epochs=10, batch=4096, lr=2e-3, beta1=0.9,
+                  beta2=0.999, eps=1e-8):
+        cfg = TrainCfg(n_polygons, data_seed, init_seed, epochs, batch, lr, beta1, beta2, eps)
+        params = np.empty(MLP_PARAMS, dtype=np.float32)
+        losses = np.empty(epochs, dtype=np.float32)
+        st = TrainStats()
+        self._check(lib().dgp_mlp_train(self._h, C.byref(cfg), params.ctypes.data, losses.ctypes.data,
+                                        C.byref(st)), "dgp_mlp_train")
+        return params, losses, st

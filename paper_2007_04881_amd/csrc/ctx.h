@@ -1,0 +1,73 @@
+// Host-side context behind the C ABI (private to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/dgpoly.h"
+#include "dgp_common.h"
+
+struct dgp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // used while capturing a graph
+    char err[512] = {0};
+
+    // mesh
+    bool has_mesh = false;
+    int dim = 2;
+    int64_t n_cells = 0, n_faces = 0, n_vertices = 0, n_cell_vtx = 0;
+    int p_uniform = -1;
+    std::vector<void *> mesh_bufs;
+    dgp::DevMesh dm{};
+
+    std::vector<int64_t> h_cell_ptr;  // loop offsets, for the assembly chunk partition
+
+    // pattern (col_idx / val_ptr sized by the upper bound n_cells + n_cell_vtx)
+    bool has_pattern = false;
+    int64_t nnzb = 0, n_vals = 0, n_dofs = 0;
+    int64_t *row_ptr = nullptr, *val_ptr = nullptr, *dof_ptr = nullptr;
+    int32_t *col_idx = nullptr;
+    // preparation outputs and the assembly's bookkeeping (one allocation)
+    void *work = nullptr;
+    dgp::PrepOut prep{};
+    int n_tiles = 0;
+
+    // assembly chunk partitions per (precision, p, rule mode)
+    int32_t *chunks[2][dgp::kMaxP + 1][2] = {};
+    int n_chunks[2][dgp::kMaxP + 1][2] = {};
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    // reduced volume rules (element data, network, fitted rules)
+    float *mlp = nullptr;          // parameters on the device
+    bool has_mlp = false;
+    bool has_qrule = false;
+    void *qr_buf = nullptr;        // one allocation, carved below
+    float *qr_feat = nullptr;      // [n_cells][36]
+    double *qr_mom = nullptr;      // [n_cells][28]
+    double *qr_area = nullptr;     // [n_cells]  |P| in box coordinates
+    double *qr_nodes = nullptr;    // [n_cells][32]
+    double *qr_w = nullptr;        // [n_cells][16]
+    double *qr_res = nullptr;      // [n_cells]
+    int32_t *qr_iters = nullptr;   // [n_cells]
+    uint8_t *qr_elig = nullptr;    // [n_cells]
+    uint8_t *qr_ok = nullptr;      // [n_cells]
+
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool ev_pattern = false, ev_assemble = false;
+};
+
+dgp_status dgp_fail(dgp_ctx *ctx, dgp_status st, const char *fmt, ...);
+void dgp_free_qrule(dgp_ctx *c);
+
+#define HIPCHK(ctx, call)                                                                                    \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess) return dgp_fail(ctx, DGP_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)

@@ -8,17 +8,22 @@ namespace dgp {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxP = 4;          // 2D kernels are built for p = 1..4
-constexpr int kTile = 256;        // cells per work-group in the pattern kernels
 constexpr int kMaxFaces2D = 24;   // faces per polygon handled by the preparation kernel
+constexpr int kPrepTile = 32;     // elements per preparation work-group (a tile)
 
-// State of the single-pass (decoupled look-back) scan over tiles of elements.
-struct Lookback {
-    unsigned long long *counter;  // tickets, never reset while the mesh lives
-    unsigned long long *status;   // per tile: (epoch << 2) | 1 aggregate, | 2 inclusive prefix
-    int64_t *agg;                 // per tile: blocks, values, dofs
-    int64_t *incl;                // per tile: inclusive prefix of the same
-    int *error;                   // set if a look-back ever gives up
-};
+// reduced volume rules: network and moment sizes
+constexpr int kQrMaxV = 12;                    // polygons with at most 12 vertices get a reduced rule
+constexpr int kQrNodes = 16;                   // nodes per reduced rule
+constexpr int kQrIn = 3 * kQrMaxV;             // 24 coordinates + 12 validity flags
+constexpr int kQrHidden = 128;
+constexpr int kQrOut = 3 * kQrNodes;           // 32 node coordinates + 16 weight logits
+constexpr int kQrMoments = 28;                 // Legendre moments of total degree <= 6
+// parameter blob: W1[36][128] b1 W2[128][128] b2 W3[128][128] b3 W4[128][48] b4 (FP32, [in][out])
+constexpr int kMlpW1 = 0, kMlpB1 = kMlpW1 + kQrIn * kQrHidden;
+constexpr int kMlpW2 = kMlpB1 + kQrHidden, kMlpB2 = kMlpW2 + kQrHidden * kQrHidden;
+constexpr int kMlpW3 = kMlpB2 + kQrHidden, kMlpB3 = kMlpW3 + kQrHidden * kQrHidden;
+constexpr int kMlpW4 = kMlpB3 + kQrHidden, kMlpB4 = kMlpW4 + kQrHidden * kQrOut;
+constexpr int kMlpParams = kMlpB4 + kQrOut;    // 43,952
 
 // Device copy of the mesh (structure of arrays, as uploaded).
 struct DevMesh {
@@ -36,7 +41,7 @@ struct DevMesh {
     const int8_t *face_bc;
 };
 
-// Per-cell geometry written by the geometry kernel, one 64-byte record per
+// Per-cell geometry written by the preparation kernel, one 64-byte record per
 // cell so that a neighbour's data is two 32-byte loads from one cache line.
 struct alignas(64) CellGeo {
     double lox, loy, hix, hiy;  // bounding box
@@ -44,6 +49,15 @@ struct alignas(64) CellGeo {
     double abar;                // max of a over the volume quadrature points
     double sqrt_box;            // sqrt(|bounding box|), basis normalisation
     double area;                // |kappa|
+};
+
+// Outputs of the preparation kernel.
+struct PrepOut {
+    CellGeo *geo;        // [n_cells]
+    int32_t *nbr;        // [loop entries] neighbour across each edge, or -boundary code
+    int32_t *cnt;        // [n_cells][4] blocks, values, dofs of the row, 0
+    int64_t *tile_sum;   // [n_tiles][3]
+    int64_t *tile_off;   // [n_tiles + 1][3] exclusive prefix of the tile sums (totals last)
 };
 
 // Problem data as the kernels see it.
@@ -88,19 +102,15 @@ struct PointData {
     double ux, uy;
 };
 
-// Manufactured data at (x, y); the load uses the closed-form derivatives of a and u.
-__device__ __forceinline__ PointData point_data(const DevProblem &pr, double x, double y, bool need_f) {
+// Manufactured data at (x, y) from sin/cos(pi x), sin/cos(pi y); the load uses
+// the closed-form derivatives of a and u.
+__device__ __forceinline__ PointData point_data_sc(const DevProblem &pr, double x, double y, double sx, double cx,
+                                                   double sy, double cy, bool need_f) {
     PointData d;
     double ax = 0.0, ay = 0.0, lap;
-    double sx = 0.0, cx = 0.0, sy = 0.0, cy = 0.0;
-    bool trig = pr.u_kind == 0 || pr.a1 != 0.0;
-    if (trig) {
-        sincospi(x, &sx, &cx);
-        sincospi(y, &sy, &cy);
-    }
     if (pr.a1 != 0.0) {
-        double s2x = 2.0 * sx * cx, c2x = cx * cx - sx * sx;
-        double s2y = 2.0 * sy * cy, c2y = cy * cy - sy * sy;
+        const double s2x = 2.0 * sx * cx, c2x = cx * cx - sx * sx;
+        const double s2y = 2.0 * sy * cy, c2y = cy * cy - sy * sy;
         d.a = pr.a0 + pr.a1 * s2x * c2y;
         ax = 2.0 * kPi * pr.a1 * c2x * c2y;
         ay = -2.0 * kPi * pr.a1 * s2x * s2y;
@@ -123,6 +133,75 @@ __device__ __forceinline__ PointData point_data(const DevProblem &pr, double x, 
     return d;
 }
 
+__device__ __forceinline__ bool needs_trig(const DevProblem &pr) { return pr.u_kind == 0 || pr.a1 != 0.0; }
+
+// Manufactured data at (x, y) with sin/cos evaluated directly (exact at integer points).
+__device__ __forceinline__ PointData point_data(const DevProblem &pr, double x, double y, bool need_f) {
+    double sx = 0.0, cx = 1.0, sy = 0.0, cy = 1.0;
+    if (needs_trig(pr)) {
+        sincospi(x, &sx, &cx);
+        sincospi(y, &sy, &cy);
+    }
+    return point_data_sc(pr, x, y, sx, cx, sy, cy, need_f);
+}
+
+// sin/cos(pi (x0 + d)) from s0 = sin(pi x0), c0 = cos(pi x0) by angle addition,
+// with sin/cos(pi d) from their Taylor series through t^11 / t^10 (t = pi d);
+// the truncation error is below 1e-18 for |t| <= kNearT.
+constexpr double kNearT = 0.2;
+__device__ __forceinline__ void sincospi_near(double s0, double c0, double d, double *s, double *c) {
+    const double t = kPi * d, t2 = t * t;
+    const double st =
+        t * (1.0 + t2 * (-1.0 / 6 + t2 * (1.0 / 120 + t2 * (-1.0 / 5040 + t2 * (1.0 / 362880 + t2 * (-1.0 / 39916800))))));
+    const double ct =
+        1.0 + t2 * (-0.5 + t2 * (1.0 / 24 + t2 * (-1.0 / 720 + t2 * (1.0 / 40320 + t2 * (-1.0 / 3628800)))));
+    *s = s0 * ct + c0 * st;
+    *c = c0 * ct - s0 * st;
+}
+
+// sin/cos(pi x), sin/cos(pi y) at an element centre, for evaluation at nearby points
+struct TrigCentre {
+    double x0, y0, sx, cx, sy, cy;
+    int near;  // the element fits within |pi d| <= kNearT of the centre
+};
+
+__device__ __forceinline__ TrigCentre trig_centre(const DevProblem &pr, double x0, double y0, double half_diam) {
+    TrigCentre t;
+    t.x0 = x0;
+    t.y0 = y0;
+    t.sx = 0.0;
+    t.cx = 1.0;
+    t.sy = 0.0;
+    t.cy = 1.0;
+    t.near = kPi * half_diam <= kNearT;
+    if (needs_trig(pr)) {
+        sincospi(x0, &t.sx, &t.cx);
+        sincospi(y0, &t.sy, &t.cy);
+    }
+    return t;
+}
+
+// Manufactured data at a point inside the element of centre t.
+__device__ __forceinline__ PointData point_data_near(const DevProblem &pr, const TrigCentre &t, double x, double y,
+                                                     bool need_f) {
+    if (!needs_trig(pr)) return point_data_sc(pr, x, y, 0.0, 1.0, 0.0, 1.0, need_f);
+    if (!t.near) return point_data(pr, x, y, need_f);
+    double sx, cx, sy, cy;
+    sincospi_near(t.sx, t.cx, x - t.x0, &sx, &cx);
+    sincospi_near(t.sy, t.cy, y - t.y0, &sy, &cy);
+    return point_data_sc(pr, x, y, sx, cx, sy, cy, need_f);
+}
+
+// Diffusion coefficient at a point inside the element of centre t.
+__device__ __forceinline__ double coef_a_near(const DevProblem &pr, const TrigCentre &t, double x, double y) {
+    if (pr.a1 == 0.0) return pr.a0;
+    if (!t.near) return coef_a(pr, x, y);
+    double sx, cx, sy, cy;
+    sincospi_near(t.sx, t.cx, x - t.x0, &sx, &cx);
+    sincospi_near(t.sy, t.cy, y - t.y0, &sy, &cy);
+    return pr.a0 + pr.a1 * (2.0 * sx * cx) * (cy * cy - sy * sy);
+}
+
 // Legendre P_0..P_n and derivatives by the three-term recurrence.
 template <typename T, int N>
 __device__ __forceinline__ void legendre(T x, T *P, T *dP) {
@@ -138,5 +217,28 @@ __device__ __forceinline__ void legendre(T x, T *P, T *dP) {
         dP[n + 1] = dP[n - 1] + T(2 * n + 1) * P[n];
     }
 }
+
+// Arguments of the assembly kernel.
+struct AsmArgs {
+    DevMesh m;
+    DevProblem pr;
+    const CellGeo *geo;
+    const int32_t *nbr;
+    const int32_t *cnt;
+    const int64_t *tile_off;
+    const int32_t *chunks;  // [n_chunks + 1][2]: first element, first loop entry
+    int64_t *row_ptr;
+    int32_t *col_idx;
+    int64_t *val_ptr;
+    int64_t *dof_ptr;
+    void *vals;
+    void *rhs;
+    int values;         // 0: pattern only
+    int write_pattern;  // write row_ptr, col_idx, val_ptr, dof_ptr
+    int reduced;        // volume matrix of accepted elements with their reduced rule
+    const double *qr_nodes;  // [n_cells][16][2] (xi, eta) in box coordinates
+    const double *qr_w;      // [n_cells][16] weights in box coordinates
+    const uint8_t *qr_ok;    // [n_cells]
+};
 
 }  // namespace dgp

@@ -8,27 +8,58 @@
 
 namespace dgp {
 
-// Geometry (always) and, with do_pattern, the block pattern, in one kernel.
-int prep_tiles(int n_cells);
-void launch_prep(const DevMesh &m, const DevProblem &pr, CellGeo *geo, bool do_pattern, const Lookback &lb,
-                 int64_t *row_ptr, int32_t *col_idx, int64_t *val_ptr, int64_t *dof_ptr, hipStream_t st);
+// Geometry, edge neighbours and row sizes, then the scan of the tile sums (two launches).
+void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st);
 
 // Capacities of one assembly work-group for (precision, p): the runtime cuts
 // the element rows into chunks of consecutive rows that respect them.
 struct AsmLimits {
     int slots;               // quadrature tasks
-    int fslots;              // face tasks
+    int fslots;              // loop edges (face tasks)
     int maxc;                // elements
-    int maxb;                // blocks
     int tasks_per_triangle;  // element-term tasks per fan sub-triangle
+    int reduced_tasks;       // element-matrix tasks per row with a reduced rule
 };
 void assemble_limits(int precision, int p, AsmLimits *lim);
 
-// Assembly of every block row; p is the common degree of all cells; chunks
-// holds n_chunks + 1 element offsets.  Returns false if no kernel is built
-// for (precision, p).
-bool launch_assemble2d(const DevMesh &m, const DevProblem &pr, const CellGeo *geo, const int64_t *row_ptr,
-                       const int32_t *col_idx, const int64_t *val_ptr, const int64_t *dof_ptr, const int32_t *chunks,
-                       int n_chunks, int precision, int p, void *vals, void *rhs, hipStream_t st);
+// Assembly (and pattern) of every block row; p is the common degree of all
+// cells.  Returns false if no kernel is built for (precision, p).
+bool launch_assemble2d(const AsmArgs &a, int n_chunks, int precision, int p, hipStream_t st);
+
+// ---- reduced volume rules
+void launch_cell_poly(const DevMesh &m, const CellGeo *geo, float *feat, double *mom, double *parea, uint8_t *eligible,
+                      hipStream_t st);
+void launch_train_poly(uint64_t seed, int64_t first, int64_t n, float *feat, double *feat64, double *mom,
+                       double *parea, hipStream_t st);
+void launch_rule_init(int n, const float *z, const double *parea, double *nodes, double *weights, hipStream_t st);
+void launch_refine(int n, const double *mom, const double *parea, const uint8_t *eligible, double *nodes,
+                   double *weights, uint8_t *accepted, double *residual, int32_t *iters, int max_it, double tol,
+                   double mu0, hipStream_t st);
+
+// ---- the rule network (FP32 on the matrix cores)
+// C = epi(A B): A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn], C row-major.
+struct GemmArgs {
+    const float *A;
+    int64_t sam, sak;
+    const float *B;
+    int64_t sbk, sbn;
+    float *C;
+    int64_t ldc;
+    int M, N, K;
+    const float *bias;  // [N] or null
+    int act;            // 0 identity, 1 SiLU (pre-activation to Zout if set), 2 times SiLU'(Z)
+    const float *Z;     // act 2: pre-activation, leading dimension ldc
+    float *Zout;
+};
+void launch_gemm(const GemmArgs &g, hipStream_t st);
+// forward pass of the network over n rows of x [n][36]; h1, h2 [n][128] scratch; out [n][48]
+void mlp_forward(const float *params, const float *x, int64_t n, float *h1, float *h2, float *out, hipStream_t st);
+// loss and gradient with respect to the 48 outputs: mean over the n rows of sum_ab (Q_ab - M_ab)^2 / |P|^2
+void launch_loss_grad(const float *out, const double *mom, const double *parea, int64_t n, int64_t n_mean, float *dout,
+                      float *loss_rows, hipStream_t st);
+// column sums of a [rows][cols] matrix into dst (deterministic)
+void launch_colsum(const float *a, int64_t rows, int cols, float *dst, hipStream_t st);
+void launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t st);
 
 }  // namespace dgp

@@ -8,52 +8,15 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dgpoly.h"
-#include "dgp_common.h"
+#include "ctx.h"
 #include "kernels.h"
 
 using namespace dgp;
 
-struct dgp_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    hipStream_t cap_stream = nullptr;  // used while capturing a graph
-    char err[512] = {0};
+#define fail dgp_fail
 
-    // mesh
-    bool has_mesh = false;
-    int dim = 2;
-    int64_t n_cells = 0, n_faces = 0, n_vertices = 0, n_cell_vtx = 0;
-    int p_uniform = -1;
-    std::vector<void *> mesh_bufs;
-    DevMesh dm{};
 
-    std::vector<int64_t> h_cell_ptr;  // loop offsets, for the assembly chunk partition
-
-    // pattern (col_idx / val_ptr sized by the upper bound n_cells + n_cell_vtx)
-    bool has_pattern = false;
-    int64_t nnzb = 0, n_vals = 0, n_dofs = 0;
-    int64_t *row_ptr = nullptr, *val_ptr = nullptr, *dof_ptr = nullptr;
-    int32_t *col_idx = nullptr;
-    Lookback lb{};
-    void *lb_mem = nullptr;
-    int n_tiles = 0;
-
-    CellGeo *geo = nullptr;
-
-    // assembly chunk partitions per (precision, p)
-    int32_t *chunks[2][kMaxP + 1] = {};
-    int n_chunks[2][kMaxP + 1] = {};
-
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-
-    bool timing = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    bool ev_pattern = false, ev_assemble = false;
-};
-
-static dgp_status fail(dgp_ctx *ctx, dgp_status st, const char *fmt, ...) {
+dgp_status dgp_fail(dgp_ctx *ctx, dgp_status st, const char *fmt, ...) {
     if (ctx) {
         va_list ap;
         va_start(ap, fmt);
@@ -63,11 +26,7 @@ static dgp_status fail(dgp_ctx *ctx, dgp_status st, const char *fmt, ...) {
     return st;
 }
 
-#define HIPCHK(ctx, call)                                                                                \
-    do {                                                                                                 \
-        hipError_t e_ = (call);                                                                          \
-        if (e_ != hipSuccess) return fail(ctx, DGP_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
+
 
 static void free_pattern(dgp_ctx *c) {
     c->has_pattern = false;
@@ -83,19 +42,19 @@ static void free_graph(dgp_ctx *c) {
 static void free_mesh(dgp_ctx *c) {
     for (void *p : c->mesh_bufs) (void)hipFree(p);
     c->mesh_bufs.clear();
-    for (void *p : {(void *)c->row_ptr, (void *)c->col_idx, (void *)c->val_ptr, (void *)c->dof_ptr,
-                    (void *)c->geo, c->lb_mem})
+    for (void *p : {(void *)c->row_ptr, (void *)c->col_idx, (void *)c->val_ptr, (void *)c->dof_ptr, c->work})
         if (p) (void)hipFree(p);
     c->row_ptr = c->val_ptr = c->dof_ptr = nullptr;
     c->col_idx = nullptr;
-    c->geo = nullptr;
-    c->lb_mem = nullptr;
+    c->work = nullptr;
     for (int q = 0; q < 2; ++q)
-        for (int p = 0; p <= kMaxP; ++p) {
-            if (c->chunks[q][p]) (void)hipFree(c->chunks[q][p]);
-            c->chunks[q][p] = nullptr;
-            c->n_chunks[q][p] = 0;
-        }
+        for (int p = 0; p <= kMaxP; ++p)
+            for (int r = 0; r < 2; ++r) {
+                if (c->chunks[q][p][r]) (void)hipFree(c->chunks[q][p][r]);
+                c->chunks[q][p][r] = nullptr;
+                c->n_chunks[q][p][r] = 0;
+            }
+    dgp_free_qrule(c);
     c->h_cell_ptr.clear();
     c->has_mesh = false;
     free_pattern(c);
@@ -145,6 +104,7 @@ dgp_status dgp_destroy(dgp_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     free_mesh(ctx);
+    if (ctx->mlp) (void)hipFree(ctx->mlp);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -240,27 +200,31 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     UP(face_cell, 2 * F, face_cell)
     UP(face_bc, F, face_bc)
 #undef UP
-    // pattern arrays at their upper bound (a row has at most 1 + #faces blocks),
-    // geometry records and the look-back state of the single-pass scan
+    // pattern arrays at their upper bound (a row has at most 1 + #faces blocks);
+    // geometry records, edge neighbours, row sizes and their tile sums
     const int64_t nnzb_max = N + nnz_v;
-    ctx->n_tiles = prep_tiles((int)N);
-    const size_t T = (size_t)ctx->n_tiles;
-    const size_t lb_bytes = 8 /*counter*/ + 8 * T /*status*/ + 24 * T /*agg*/ + 24 * T /*incl*/ + 8 /*error*/;
+    ctx->n_tiles = (int)((N + kPrepTile - 1) / kPrepTile);
+    const size_t o_geo = 0;
+    const size_t o_nbr = o_geo + sizeof(CellGeo) * (size_t)N;
+    const size_t o_cnt = o_nbr + ((sizeof(int32_t) * (size_t)nnz_v + 255) & ~size_t(255));
+    const size_t o_tile = o_cnt + sizeof(int32_t) * 4 * (size_t)N;
+    const size_t o_off = o_tile + ((sizeof(int64_t) * 3 * (size_t)ctx->n_tiles + 255) & ~size_t(255));
+    const size_t work_bytes = o_off + sizeof(int64_t) * 3 * (size_t)(ctx->n_tiles + 1);
     if (hipMalloc(&ctx->row_ptr, sizeof(int64_t) * (N + 1)) != hipSuccess ||
         hipMalloc(&ctx->col_idx, sizeof(int32_t) * nnzb_max) != hipSuccess ||
         hipMalloc(&ctx->val_ptr, sizeof(int64_t) * (nnzb_max + 1)) != hipSuccess ||
         hipMalloc(&ctx->dof_ptr, sizeof(int64_t) * (N + 1)) != hipSuccess ||
-        hipMalloc(&ctx->geo, sizeof(CellGeo) * N) != hipSuccess || hipMalloc(&ctx->lb_mem, lb_bytes) != hipSuccess) {
+        hipMalloc(&ctx->work, work_bytes) != hipSuccess) {
         free_mesh(ctx);
         return fail(ctx, DGP_ENOMEM, "device allocation failed");
     }
-    HIPCHK(ctx, hipMemset(ctx->lb_mem, 0, lb_bytes));
-    char *b = static_cast<char *>(ctx->lb_mem);
-    ctx->lb.counter = reinterpret_cast<unsigned long long *>(b);
-    ctx->lb.status = reinterpret_cast<unsigned long long *>(b + 8);
-    ctx->lb.agg = reinterpret_cast<int64_t *>(b + 8 + 8 * T);
-    ctx->lb.incl = reinterpret_cast<int64_t *>(b + 8 + 32 * T);
-    ctx->lb.error = reinterpret_cast<int *>(b + 8 + 56 * T);
+    HIPCHK(ctx, hipMemset(ctx->work, 0, work_bytes));
+    char *b = static_cast<char *>(ctx->work);
+    ctx->prep.geo = reinterpret_cast<CellGeo *>(b + o_geo);
+    ctx->prep.nbr = reinterpret_cast<int32_t *>(b + o_nbr);
+    ctx->prep.cnt = reinterpret_cast<int32_t *>(b + o_cnt);
+    ctx->prep.tile_sum = reinterpret_cast<int64_t *>(b + o_tile);
+    ctx->prep.tile_off = reinterpret_cast<int64_t *>(b + o_off);
     ctx->h_cell_ptr.assign(m->cell_ptr, m->cell_ptr + N + 1);
     ctx->has_mesh = true;
     return DGP_OK;
@@ -273,22 +237,27 @@ static DevProblem neutral_problem() {
     return d;
 }
 
+static dgp_status prepare_chunks(dgp_ctx *ctx, int precision, int p, int rule_mode);
+static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
+                               int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed);
+
 dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
     if (!ctx || !out) return DGP_EINVAL;
     if (!ctx->has_mesh) return fail(ctx, DGP_ESTATE, "dgp_pattern before dgp_mesh_upload");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     free_pattern(ctx);
     free_graph(ctx);
-    launch_prep(ctx->dm, neutral_problem(), ctx->geo, true, ctx->lb, ctx->row_ptr, ctx->col_idx, ctx->val_ptr,
-                ctx->dof_ptr, ctx->stream);
-    HIPCHK(ctx, hipGetLastError());
+    const int p = ctx->p_uniform;
+    if (p < 1 || p > 3)
+        return fail(ctx, DGP_EUNSUPPORTED, "this version assembles meshes of one common degree p in 1..3");
+    dgp_status st = prepare_chunks(ctx, DGP_F64, p, DGP_RULE_PLAIN);
+    if (st) return st;
+    st = enqueue_step(ctx, neutral_problem(), DGP_F64, DGP_RULE_PLAIN, 0, 1, nullptr, nullptr, ctx->stream, false);
+    if (st) return st;
     int64_t tot[3];
-    int err = 0;
-    HIPCHK(ctx, hipMemcpyAsync(tot, ctx->lb.incl + 3 * (ctx->n_tiles - 1), sizeof(tot), hipMemcpyDeviceToHost,
+    HIPCHK(ctx, hipMemcpyAsync(tot, ctx->prep.tile_off + 3 * ctx->n_tiles, sizeof(tot), hipMemcpyDeviceToHost,
                                ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(&err, ctx->lb.error, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    if (err) return fail(ctx, DGP_EDEVICE, "pattern scan look-back did not complete");
     ctx->nnzb = tot[0];
     ctx->n_vals = tot[1];
     ctx->n_dofs = tot[2];
@@ -329,9 +298,8 @@ static DevProblem to_dev(const dgp_problem *p) {
     return d;
 }
 
-static dgp_status prepare_chunks(dgp_ctx *ctx, int precision, int p);
-
-static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs) {
+static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode, void *vals,
+                                      void *rhs) {
     if (!ctx || !prob || !vals || !rhs) return fail(ctx, DGP_EINVAL, "null argument");
     if (!ctx->has_pattern) return fail(ctx, DGP_ESTATE, "assembly before dgp_pattern");
     if (precision != DGP_F64 && precision != DGP_F32) return fail(ctx, DGP_EINVAL, "precision %d", precision);
@@ -339,52 +307,80 @@ static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int
     if (!(prob->c_sigma >= 0.0)) return fail(ctx, DGP_EINVAL, "c_sigma must be >= 0");
     if (ctx->p_uniform < 1 || ctx->p_uniform > 3)
         return fail(ctx, DGP_EUNSUPPORTED, "this version assembles meshes of one common degree p in 1..3");
-    return prepare_chunks(ctx, precision, ctx->p_uniform);
+    if (rule_mode != DGP_RULE_PLAIN && rule_mode != DGP_RULE_REDUCED)
+        return fail(ctx, DGP_EINVAL, "rule_mode %d", rule_mode);
+    if (rule_mode == DGP_RULE_REDUCED) {
+        if (!ctx->has_qrule) return fail(ctx, DGP_ESTATE, "reduced rules requested before dgp_qrule_build");
+        if (prob->a1 != 0.0)
+            return fail(ctx, DGP_EINVAL, "reduced rules integrate polynomials of degree <= 6: a must be constant");
+        if (ctx->p_uniform > 3) return fail(ctx, DGP_EUNSUPPORTED, "reduced rules need p <= 3");
+    }
+    return prepare_chunks(ctx, precision, ctx->p_uniform, rule_mode);
 }
 
-// Cut the rows into chunks of consecutive rows whose quadrature tasks, face
-// tasks, elements and (upper-bound) blocks fit one assembly work-group.
-static dgp_status prepare_chunks(dgp_ctx *ctx, int precision, int p) {
-    if (ctx->chunks[precision][p]) return DGP_OK;
+// Cut the rows into chunks of consecutive rows whose quadrature tasks, loop
+// edges and elements fit one assembly work-group.  The table holds, per
+// chunk, its first element and its first loop entry (plus a sentinel).
+static dgp_status prepare_chunks(dgp_ctx *ctx, int precision, int p, int rule_mode) {
+    if (ctx->chunks[precision][p][rule_mode]) return DGP_OK;
     AsmLimits lim;
     assemble_limits(precision, p, &lim);
     if (lim.slots == 0) return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
-    std::vector<int32_t> starts{0};
-    int tasks = 0, faces = 0, cells = 0, blocks = 0;
+    std::vector<int32_t> tab{0, 0};
+    int tasks = 0, faces = 0, cells = 0;
     for (int64_t c = 0; c < ctx->n_cells; ++c) {
         const int nv = (int)(ctx->h_cell_ptr[c + 1] - ctx->h_cell_ptr[c]);
-        const int t = (nv - 2) * lim.tasks_per_triangle + nv, b = nv + 1;
-        if (t > lim.slots || nv > lim.fslots || b > lim.maxb)
+        const int t = (nv - 2) * lim.tasks_per_triangle + nv + (rule_mode ? lim.reduced_tasks : 0);
+        if (t > lim.slots || nv > lim.fslots)
             return fail(ctx, DGP_EUNSUPPORTED, "cell %lld is too large for one work-group", (long long)c);
-        if (tasks + t > lim.slots || faces + nv > lim.fslots || cells + 1 > lim.maxc || blocks + b > lim.maxb) {
-            starts.push_back((int32_t)c);
-            tasks = faces = cells = blocks = 0;
+        if (tasks + t > lim.slots || faces + nv > lim.fslots || cells + 1 > lim.maxc) {
+            tab.push_back((int32_t)c);
+            tab.push_back((int32_t)ctx->h_cell_ptr[c]);
+            tasks = faces = cells = 0;
         }
         tasks += t;
         faces += nv;
         cells += 1;
-        blocks += b;
     }
-    starts.push_back((int32_t)ctx->n_cells);
+    tab.push_back((int32_t)ctx->n_cells);
+    tab.push_back((int32_t)ctx->h_cell_ptr[ctx->n_cells]);
     int32_t *d = nullptr;
-    if (hipMalloc(&d, sizeof(int32_t) * starts.size()) != hipSuccess)
+    if (hipMalloc(&d, sizeof(int32_t) * tab.size()) != hipSuccess)
         return fail(ctx, DGP_ENOMEM, "chunk table allocation failed");
-    HIPCHK(ctx, hipMemcpy(d, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice));
-    ctx->chunks[precision][p] = d;
-    ctx->n_chunks[precision][p] = (int)starts.size() - 1;
+    HIPCHK(ctx, hipMemcpy(d, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice));
+    ctx->chunks[precision][p][rule_mode] = d;
+    ctx->n_chunks[precision][p][rule_mode] = (int)tab.size() / 2 - 1;
     return DGP_OK;
 }
 
-static dgp_status enqueue_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs,
-                                   hipStream_t st, bool with_pattern, bool timed) {
-    DevProblem dp = to_dev(prob);
+// One step: preparation kernel, then the assembly kernel (values = 0: pattern only).
+static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
+                               int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed) {
     const int p = ctx->p_uniform;
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
-    launch_prep(ctx->dm, dp, ctx->geo, with_pattern, ctx->lb, ctx->row_ptr, ctx->col_idx, ctx->val_ptr,
-                ctx->dof_ptr, st);
+    launch_prep(ctx->dm, dp, ctx->prep, st);
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
-    if (!launch_assemble2d(ctx->dm, dp, ctx->geo, ctx->row_ptr, ctx->col_idx, ctx->val_ptr, ctx->dof_ptr,
-                           ctx->chunks[precision][p], ctx->n_chunks[precision][p], precision, p, vals, rhs, st))
+    AsmArgs a;
+    a.m = ctx->dm;
+    a.pr = dp;
+    a.geo = ctx->prep.geo;
+    a.nbr = ctx->prep.nbr;
+    a.cnt = ctx->prep.cnt;
+    a.tile_off = ctx->prep.tile_off;
+    a.chunks = ctx->chunks[precision][p][rule_mode];
+    a.row_ptr = ctx->row_ptr;
+    a.col_idx = ctx->col_idx;
+    a.val_ptr = ctx->val_ptr;
+    a.dof_ptr = ctx->dof_ptr;
+    a.vals = vals;
+    a.rhs = rhs;
+    a.values = values;
+    a.write_pattern = write_pattern;
+    a.reduced = rule_mode == DGP_RULE_REDUCED;
+    a.qr_nodes = ctx->qr_nodes;
+    a.qr_w = ctx->qr_w;
+    a.qr_ok = ctx->qr_ok;
+    if (!launch_assemble2d(a, ctx->n_chunks[precision][p][rule_mode], precision, p, st))
         return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[2], st));
     HIPCHK(ctx, hipGetLastError());
@@ -393,29 +389,35 @@ static dgp_status enqueue_assemble(dgp_ctx *ctx, const dgp_problem *prob, int pr
     return DGP_OK;
 }
 
-dgp_status dgp_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs) {
-    dgp_status st = check_assemble_args(ctx, prob, precision, vals, rhs);
-    if (st) return st;
-    HIPCHK(ctx, hipSetDevice(ctx->device));
-    return enqueue_assemble(ctx, prob, precision, vals, rhs, ctx->stream, false, ctx->timing);
+static dgp_status enqueue_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode,
+                                   int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed) {
+    return enqueue_step(ctx, to_dev(prob), precision, rule_mode, 1, write_pattern, vals, rhs, st, timed);
 }
 
-dgp_status dgp_run(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs) {
-    dgp_status st = check_assemble_args(ctx, prob, precision, vals, rhs);
+dgp_status dgp_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode, void *vals, void *rhs) {
+    dgp_status st = check_assemble_args(ctx, prob, precision, rule_mode, vals, rhs);
     if (st) return st;
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    return enqueue_assemble(ctx, prob, precision, vals, rhs, ctx->stream, true, ctx->timing);
+    return enqueue_assemble(ctx, prob, precision, rule_mode, 0, vals, rhs, ctx->stream, ctx->timing);
 }
 
-dgp_status dgp_graph_capture(dgp_ctx *ctx, int what, const dgp_problem *prob, int precision, void *vals, void *rhs) {
-    dgp_status st = check_assemble_args(ctx, prob, precision, vals, rhs);
+dgp_status dgp_run(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode, void *vals, void *rhs) {
+    dgp_status st = check_assemble_args(ctx, prob, precision, rule_mode, vals, rhs);
+    if (st) return st;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return enqueue_assemble(ctx, prob, precision, rule_mode, 1, vals, rhs, ctx->stream, ctx->timing);
+}
+
+dgp_status dgp_graph_capture(dgp_ctx *ctx, int what, const dgp_problem *prob, int precision, int rule_mode,
+                             void *vals, void *rhs) {
+    dgp_status st = check_assemble_args(ctx, prob, precision, rule_mode, vals, rhs);
     if (st) return st;
     if (what != 0 && what != 1) return fail(ctx, DGP_EINVAL, "what = %d", what);
     HIPCHK(ctx, hipSetDevice(ctx->device));
     free_graph(ctx);
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    st = enqueue_assemble(ctx, prob, precision, vals, rhs, ctx->cap_stream, what == 0, false);
+    st = enqueue_assemble(ctx, prob, precision, rule_mode, what == 0 ? 1 : 0, vals, rhs, ctx->cap_stream, false);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (st) {

@@ -27,7 +27,8 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_layouts_match_header(tmp_path):
     """Compile a C program against the header and compare every field offset."""
-    structs = {"dgp_mesh_desc": D.MeshDesc, "dgp_problem": D.ProblemDesc, "dgp_pattern_info": D.PatternInfo}
+    structs = {"dgp_mesh_desc": D.MeshDesc, "dgp_problem": D.ProblemDesc, "dgp_pattern_info": D.PatternInfo,
+               "dgp_qrule_stats": D.QruleStats, "dgp_train_cfg": D.TrainCfg, "dgp_train_stats": D.TrainStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dgpoly.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
