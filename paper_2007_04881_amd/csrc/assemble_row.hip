@@ -1,0 +1,513 @@
+// 2D SIPG assembly, one wave per element row (row-owner form, no atomics).
+//
+// A wave owns element row r.  Its lanes first hold the loop edges (start
+// vertex, neighbour across the edge, the rank and value offset of the
+// neighbour's block, as the preparation kernel recorded them), and the row's
+// offsets come from the scanned tile sums plus the element's prefix inside its
+// tile; with them the wave writes its row of the block pattern (Section 3.4,
+// Approach 2: one block per distinct neighbour, columns ascending).  Then
+// every lane takes one quadrature point of the row: a point of a fan
+// sub-triangle (element term, first line of eq. dg-bilinear, and the load of
+// eq. dg-linear) or a point of an edge (the face lines of both equations).
+// Edges are handled in groups of FG lanes, one group per neighbour (every
+// edge shared with it, in loop order) or per boundary edge, so each cross
+// block is summed inside its group.
+//
+// Every term at a point is a rank-3 update in the row's test functions
+// (u_0, u_1, u_2) = (d phi / d xi, d phi / d eta, phi):
+//     D_ij += sum_a u_a(i) t_a(j),   t_0 = a0 g0 + b0 v,  t_1 = a1 g1 + b1 v,
+//                                    t_2 = c0 g0 + c1 g1 + c2 v     (trial = own basis)
+//     X_ij += sum_a u_a(i) s_a(j),   s from the neighbour's basis
+//     F_i  += sum_a u_a(i) r_a
+// with, written for the test functions phi_i of row r (dn = grad phi . n_r,
+// primes = the neighbour's basis, bn = b . n_r, w the point weight):
+//   element:  a0 = w a cx^2, a1 = w a cy^2, (c0, c1, c2) = w (b_x cx, b_y cy, c), r_2 = w f
+//   interior: b0 = ha cnx, b1 = ha cny, (c0, c1, c2) = (ha cnx, ha cny, hs),
+//             s_0 = -ha cnx v', s_1 = -ha cny v', s_2 = ha dn' - hs v',
+//             ha = -w a / 2, hs = w (sigma - [bn < 0] bn)
+//   boundary: as interior with ha = -w a and no cross block;
+//             (r_0, r_1, r_2) = (cnx ga, cny ga, gs), ga = -w a g, gs = hs g
+//   Neumann:  r_2 = w g_N
+// (cx, cy = 2 / box sides; cnx = cx n_x).  Lanes accumulate the element block
+// and the load in registers over their points; a reduce-scatter across the
+// wave then leaves entry e in lane e (a coalesced write).  Cross blocks are
+// summed column by column inside their group and written directly.  Large
+// element blocks are built in column slices of JS columns to bound registers.
+//
+// Precision: positions, Jacobians, box factors, coefficients, the load and the
+// penalty are FP64; the point coefficients are rounded once to T and the
+// basis is evaluated in T.  The basis normalisation s_i s'_j is applied to the
+// finished sums in FP64.
+#include <utility>
+
+#include "asm_common.h"
+#include "kernels.h"
+
+namespace dgp {
+
+namespace {
+
+// P: degree of the row's element; PN: largest degree of its neighbours
+template <typename T, int P, int PN>
+struct RowCfg {
+    static constexpr int NB = nb2d(P);
+    static constexpr int NBN = nb2d(PN);
+    static constexpr int NB2 = NB * NB;
+    static constexpr int JS = sizeof(T) == 4 ? (P <= 2 ? NB : P == 3 ? 5 : 3) : (P == 1 ? 3 : P == 2 ? 3 : 2);
+    static constexpr int NSL = (NB + JS - 1) / JS;
+    static constexpr int ED = NB * JS;  // element-block entries per slice
+    static constexpr int E = ED + NB;   // with the load vector
+    static_assert(E <= 64, "one entry per lane after the reduction");
+    static constexpr int PF = P > PN ? P : PN;
+    static constexpr int NG = PF + 1 > 3 ? PF + 1 : 3;  // Gauss points per edge, at most
+    static constexpr int FG = NG <= 4 ? 4 : 8;         // lanes per edge group
+    static constexpr int TDEG = P <= 2 ? 4 : 2 * P;
+    static constexpr int NQT = Tri<TDEG>::n;
+};
+
+// Reduce-scatter over the 64 lanes: on return a[0] of lane l is the sum over
+// lanes of entry l.  EC = entries that may be nonzero (a[EC..] are zero).
+template <typename T, int O, int EC>
+struct WaveRS {
+    __device__ static __forceinline__ void run(T (&a)[64], int lane) {
+        constexpr int NP = O < EC ? O : EC;
+        const bool up = (lane & O) != 0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const T lo = a[k];
+            const T hi = (k + O < EC) ? a[k + O] : T(0);
+            const T send = up ? lo : hi;
+            const T keep = up ? hi : lo;
+            a[k] = keep + __shfl_xor(send, O, 64);
+        }
+        WaveRS<T, O / 2, (O < EC ? O : EC)>::run(a, lane);
+    }
+};
+template <typename T, int EC>
+struct WaveRS<T, 0, EC> {
+    __device__ static __forceinline__ void run(T (&)[64], int) {}
+};
+
+// A wave-uniform double moved to scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Per-point coefficients of the rank-3 updates (see the file comment).
+template <typename T>
+struct PointCoef {
+    T a0, b0, a1, b1, c0, c1, c2;  // element block
+    T s0, s1, x0, x1, x2;          // cross block: s_0 = s0 v', s_1 = s1 v', s_2 = x0 g0' + x1 g1' + x2 v'
+    T r0, r1, r2;                  // load
+    __device__ __forceinline__ void zero() {
+        a0 = b0 = a1 = b1 = c0 = c1 = c2 = s0 = s1 = x0 = x1 = x2 = r0 = r1 = r2 = T(0);
+    }
+};
+
+// Everything a slice of the row needs, computed once per row.
+struct RowCtx {
+    int lane, c, nv, vid, o, voff, dvoff, maxdup, QM, QF0, Qtot, QR;
+    bool red;
+    uint64_t gmask;
+    double ex, ey, isq, hx, hy, pen_r;
+    int64_t pre_v, pre_d;
+    Box bx;
+    TrigCentre tc;
+};
+
+template <typename T, int P, int PN, bool ADV, int SL>
+__device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
+    using C = RowCfg<T, P, PN>;
+    constexpr int NB = C::NB, JS = C::JS, FG = C::FG, ED = C::ED;
+    constexpr int j0 = SL * JS;
+    const DevMesh &m = A.m;
+    const DevProblem &pr = A.pr;
+    T *__restrict__ vals = static_cast<T *>(A.vals);
+    T *__restrict__ rhs = static_cast<T *>(A.rhs);
+    const int lane = R.lane, c = R.c, nv = R.nv, vid = R.vid, o = R.o, voff = R.voff;
+    const int QM = R.QM, QF0 = R.QF0, Qtot = R.Qtot;
+    const double ex = R.ex, ey = R.ey;
+    const Box &bx = R.bx;
+    const TrigCentre &tc = R.tc;
+    using R_ = Tri<C::TDEG>;
+
+    T acc[64];
+#pragma unroll
+    for (int e = 0; e < 64; ++e) acc[e] = T(0);  // [0, ED): element block slice, [ED, ED + NB): load
+
+    for (int base = 0; base < Qtot; base += 64) {
+        const int q = base + lane;
+        const bool edge_lane = q >= QF0 && q < Qtot;
+        const int gi = edge_lane ? (q - QF0) / FG : 0;
+        const int gq = edge_lane ? (q - QF0) - gi * FG : 0;
+        // leader edge of the lane's group
+        int fl = 0;
+        for (int k = 0; k < nv; ++k)
+            if (((R.gmask >> k) & 1ull) && __popcll(R.gmask & ((1ull << k) - 1ull)) == gi) fl = k;
+        const int og = __shfl(o, fl, 64);
+        const int gvoff = __shfl(voff, fl, 64);
+        const bool cross = edge_lane && og >= 0;
+        CellGeo go{};
+        double pen_o = 0.0;
+        int po = P;  // degree across the edge (the row's own on the boundary)
+        if (cross) {
+            go = A.geo[og];
+            po = PN == P ? P : m.cell_p[og];
+            pen_o = go.abar * po * po / go.h;
+        }
+        const int nbo = nb2d(po);
+        const int ngf = (P > po ? P : po) + 1 > 3 ? (P > po ? P : po) + 1 : 3;  // this edge's Gauss points
+        const double xsc = cross ? R.isq / go.sqrt_box : 0.0;
+        const bool pass_has_edges = base + 64 > QF0 && base < Qtot;
+
+        for (int d = 0; d < R.maxdup; ++d) {
+            // the lane's point: an element point (d == 0) or point gq of the d-th edge of its group
+            int fk = fl;
+            if (d > 0) {
+                int seen = 0;
+                fk = -1;
+                for (int k = 0; k < nv; ++k) {
+                    const int ok = __shfl(o, k, 64);
+                    if (og >= 0 && ok == og) {
+                        if (seen == d) fk = k;
+                        ++seen;
+                    }
+                }
+            }
+            const bool vol = d == 0 && q < QM;
+            const bool epnt = edge_lane && gq < ngf && fk >= 0;
+            const int tri = vol && !R.red ? q / C::NQT : 0;
+            const int s1 = vol ? tri + 1 : (fk >= 0 ? fk : 0);
+            const int s2 = vol ? tri + 2 : (fk >= 0 ? (fk + 1 == nv ? 0 : fk + 1) : 0);
+            const double X0 = __shfl(ex, 0, 64), Y0 = __shfl(ey, 0, 64);
+            const double X1 = __shfl(ex, s1, 64), Y1 = __shfl(ey, s1, 64);
+            const double X2 = __shfl(ex, s2, 64), Y2 = __shfl(ey, s2, 64);
+            const int V1 = __shfl(vid, s1, 64), V2 = __shfl(vid, s2, 64);
+
+            PointCoef<T> pc;
+            pc.zero();
+            double xi = 0.0, eta = 0.0, xin = 0.0, etan = 0.0;
+            if (vol && !R.red) {
+                const int qi = q - tri * C::NQT;
+                const double area = 0.5 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
+                const double l0 = R_::l(3 * qi), l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
+                const double px = l0 * X0 + l1 * X1 + l2 * X2, py = l0 * Y0 + l1 * Y1 + l2 * Y2;
+                const double W = R_::w(qi) * area;
+                const PointData pd = point_data_near(pr, tc, px, py, SL == 0);
+                xi = (px - bx.mx) * bx.cx;
+                eta = (py - bx.my) * bx.cy;
+                pc.a0 = T(W * bx.cx * bx.cx * pd.a);
+                pc.a1 = T(W * bx.cy * bx.cy * pd.a);
+                if (ADV) {
+                    pc.c0 = T(W * pr.bx * bx.cx);
+                    pc.c1 = T(W * pr.by * bx.cy);
+                    pc.c2 = T(W * pr.c);
+                }
+                pc.r2 = T(W * pd.f);
+            } else if (vol) {
+                // reduced rule: node q of the element's accepted rule (box coordinates)
+                xi = A.qr_nodes[(int64_t)c * 2 * kQrNodes + 2 * q];
+                eta = A.qr_nodes[(int64_t)c * 2 * kQrNodes + 2 * q + 1];
+                const double W = A.qr_w[(int64_t)c * kQrNodes + q] * 0.25 * R.hx * R.hy;
+                const double a = coef_a_near(pr, tc, bx.mx + xi / bx.cx, bx.my + eta / bx.cy);
+                pc.a0 = T(W * bx.cx * bx.cx * a);
+                pc.a1 = T(W * bx.cy * bx.cy * a);
+                if (ADV) {
+                    pc.c0 = T(W * pr.bx * bx.cx);
+                    pc.c1 = T(W * pr.by * bx.cy);
+                    pc.c2 = T(W * pr.c);
+                }
+            } else if (epnt) {
+                // edge (v_fk, v_fk+1); points in canonical order (lower vertex id first)
+                const bool fwd = V1 < V2;
+                const double xa = fwd ? X1 : X2, ya = fwd ? Y1 : Y2;
+                const double tx = (fwd ? X2 : X1) - xa, ty = (fwd ? Y2 : Y1) - ya;
+                const double len = sqrt(tx * tx + ty * ty);
+                const double dir = fwd ? 1.0 : -1.0;
+                const double nx = dir * ty / len, ny = -dir * tx / len;  // outward for a CCW loop
+                const double bn = pr.bx * nx + pr.by * ny;
+                const double up = bn < 0.0 ? bn : 0.0;
+                const int goff = c_gl_off[ngf - 1];
+                const double tq = c_gl_t[goff + gq], w = c_gl_w[goff + gq] * len;
+                const double px = xa + tq * tx, py = ya + tq * ty;
+                const double cnx = bx.cx * nx, cny = bx.cy * ny;
+                xi = (px - bx.mx) * bx.cx;
+                eta = (py - bx.my) * bx.cy;
+                if (og >= 0) {
+                    const Box bo = box_of(go);
+                    const double sigma = pr.c_sigma * (R.pen_r > pen_o ? R.pen_r : pen_o);
+                    const double ha = -0.5 * w * coef_a_near(pr, tc, px, py), hs = (sigma - up) * w;
+                    pc.b0 = T(ha * cnx);
+                    pc.b1 = T(ha * cny);
+                    pc.c0 = T(ha * cnx);
+                    pc.c1 = T(ha * cny);
+                    pc.c2 = T(hs);
+                    pc.s0 = T(-ha * cnx);
+                    pc.s1 = T(-ha * cny);
+                    pc.x0 = T(ha * bo.cx * nx);
+                    pc.x1 = T(ha * bo.cy * ny);
+                    pc.x2 = T(-hs);
+                    xin = (px - bo.mx) * bo.cx;
+                    etan = (py - bo.my) * bo.cy;
+                } else if (og == -1) {
+                    const double sigma = pr.c_sigma * R.pen_r;
+                    const PointData pd = point_data(pr, px, py, false);
+                    const double ha = -w * pd.a, hs = (sigma - up) * w;
+                    pc.b0 = T(ha * cnx);
+                    pc.b1 = T(ha * cny);
+                    pc.c0 = T(ha * cnx);
+                    pc.c1 = T(ha * cny);
+                    pc.c2 = T(hs);
+                    pc.r0 = T(ha * pd.u * cnx);
+                    pc.r1 = T(ha * pd.u * cny);
+                    pc.r2 = T(hs * pd.u);
+                } else {
+                    const PointData pd = point_data(pr, px, py, false);
+                    pc.r2 = T(w * pd.a * (pd.ux * nx + pd.uy * ny));
+                }
+            }
+            Eval<T, P> ev;
+            ev.at(T(xi), T(eta));
+#pragma unroll
+            for (int jj = 0; jj < JS; ++jj) {
+                const int j = j0 + jj;
+                if (j < NB) {
+                    const T t0 = fmat(pc.a0, ev.g0[j], pc.b0 * ev.v[j]);
+                    const T t1 = fmat(pc.a1, ev.g1[j], pc.b1 * ev.v[j]);
+                    const T t2 = fmat(pc.c0, ev.g0[j], fmat(pc.c1, ev.g1[j], pc.c2 * ev.v[j]));
+#pragma unroll
+                    for (int i = 0; i < NB; ++i)
+                        acc[i * JS + jj] = fmat(ev.g0[i], t0, fmat(ev.g1[i], t1, fmat(ev.v[i], t2, acc[i * JS + jj])));
+                }
+            }
+            if (SL == 0) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    acc[ED + i] = fmat(ev.g0[i], pc.r0, fmat(ev.g1[i], pc.r1, fmat(ev.v[i], pc.r2, acc[ED + i])));
+            }
+            if (pass_has_edges) {
+                // cross block, one column at a time: the group's lanes sum the column
+                // (butterfly inside the group) and lane gq writes the entries i = gq mod FG
+                T Lx[PN + 1], dLx[PN + 1], Ly[PN + 1], dLy[PN + 1];
+                legendre<T, PN>(T(xin), Lx, dLx);
+                legendre<T, PN>(T(etan), Ly, dLy);
+                T *dst = vals + R.pre_v + gvoff;
+                const bool wr = cross && fk >= 0;
+                // trial columns of the neighbour's block: all of them, in slices of the row's width
+                constexpr int NSX = (C::NBN + JS - 1) / JS;
+#pragma unroll
+                for (int sx = (SL < NSX ? SL : NSX); sx < (SL + 1 < C::NSL ? SL + 1 : NSX); ++sx)
+#pragma unroll
+                for (int jj = 0; jj < JS; ++jj) {
+                    const int j = sx * JS + jj;
+                    if (j < C::NBN && j < nbo) {
+                        const T vj = Lx[exp_a(j)] * Ly[exp_b(j)];
+                        const T gj0 = dLx[exp_a(j)] * Ly[exp_b(j)], gj1 = Lx[exp_a(j)] * dLy[exp_b(j)];
+                        const T u0 = pc.s0 * vj, u1 = pc.s1 * vj;
+                        const T u2 = fmat(pc.x0, gj0, fmat(pc.x1, gj1, pc.x2 * vj));
+                        T col[NB];
+#pragma unroll
+                        for (int i = 0; i < NB; ++i) col[i] = fmat(ev.g0[i], u0, fmat(ev.g1[i], u1, ev.v[i] * u2));
+#pragma unroll
+                        for (int off = 1; off < FG; off <<= 1)
+#pragma unroll
+                            for (int i = 0; i < NB; ++i) col[i] += __shfl_xor(col[i], off, 64);
+                        if (wr) {
+#pragma unroll
+                            for (int i = 0; i < NB; ++i)
+                                if (i % FG == gq) {
+                                    const T v = T(double(col[i]) * (c_norm[i] * c_norm[j] * xsc));
+                                    if (d == 0)
+                                        dst[i * nbo + j] = v;
+                                    else
+                                        dst[i * nbo + j] += v;
+                                }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // load-only points of rows with a reduced rule (fan sub-triangles)
+    if (SL == 0) {
+        for (int base = 0; base < R.QR; base += 64) {
+            const int q = base + lane;
+            const int tri = q < R.QR ? q / C::NQT : 0;
+            const double X0 = __shfl(ex, 0, 64), Y0 = __shfl(ey, 0, 64);
+            const double X1 = __shfl(ex, tri + 1, 64), Y1 = __shfl(ey, tri + 1, 64);
+            const double X2 = __shfl(ex, tri + 2, 64), Y2 = __shfl(ey, tri + 2, 64);
+            if (q < R.QR) {
+                const int qi = q - tri * C::NQT;
+                const double area = 0.5 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
+                const double l0 = R_::l(3 * qi), l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
+                const double px = l0 * X0 + l1 * X1 + l2 * X2, py = l0 * Y0 + l1 * Y1 + l2 * Y2;
+                const PointData pd = point_data_near(pr, tc, px, py, true);
+                const T wf = T(R_::w(qi) * area * pd.f);
+                T Lx[P + 1], dLx[P + 1], Ly[P + 1], dLy[P + 1];
+                legendre<T, P>(T((px - bx.mx) * bx.cx), Lx, dLx);
+                legendre<T, P>(T((py - bx.my) * bx.cy), Ly, dLy);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) acc[ED + i] = fmat(wf, Lx[exp_a(i)] * Ly[exp_b(i)], acc[ED + i]);
+            }
+        }
+    }
+    // element block slice and load: reduce-scatter over the wave, lane e writes entry e
+    WaveRS<T, 32, (SL == 0 ? C::E : ED)>::run(acc, lane);
+    if (lane < ED) {
+        const int i = lane / JS, j = j0 + (lane - i * JS);
+        if (j < NB) vals[R.pre_v + R.dvoff + i * NB + j] = T(double(acc[0]) * (c_norm[i] * c_norm[j] * R.isq * R.isq));
+    } else if (SL == 0 && lane < C::E) {
+        const int i = lane - ED;
+        rhs[R.pre_d + i] = T(double(acc[0]) * (c_norm[i] * R.isq));
+    }
+}
+
+template <typename T, int P, int PN, bool ADV, int... SL>
+__device__ __forceinline__ void row_slices(const AsmArgs &A, const RowCtx &R, std::integer_sequence<int, SL...>) {
+    (row_slice<T, P, PN, ADV, SL>(A, R), ...);
+}
+
+}  // namespace
+
+template <typename T, int P, int PN, bool ADV>
+__global__ void __launch_bounds__(256) k_row2d(AsmArgs A) {
+    using C = RowCfg<T, P, PN>;
+    constexpr int NB = C::NB, FG = C::FG;
+    const DevMesh &m = A.m;
+    const DevProblem &pr = A.pr;
+    const int lane = threadIdx.x & 63;
+    // the row index is uniform across the wave: keep it (and what derives from it) in scalar registers
+    const int wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wid >= A.n_rows) return;
+    const int c = A.rows ? __builtin_amdgcn_readfirstlane(A.rows[wid]) : wid;
+    const int64_t s = m.cell_ptr[c];
+    const int nv = (int)(m.cell_ptr[c + 1] - s);
+
+    // ---- the row's offsets (scanned tile sums plus the element's prefix inside its tile)
+    const int t0 = c / kPrepTile;
+    const int4 cr = reinterpret_cast<const int4 *>(A.cnt)[c];
+    const int64_t pre_b = A.tile_off[3 * t0] + cr.x;
+    const int64_t pre_v = A.tile_off[3 * t0 + 1] + cr.y;
+    const int64_t pre_d = A.tile_off[3 * t0 + 2] + cr.z;
+    const int drank = cr.w & 255, dvoff = cr.w >> 8;
+
+    // ---- loop edges, one per lane
+    int vid = 0, o = -3, rank = 0, voff = 0;
+    bool first = false;
+    double ex = 0.0, ey = 0.0;
+    if (lane < nv) {
+        const EdgeRec er = A.erec[s + lane];
+        ex = er.x;
+        ey = er.y;
+        vid = er.vid;
+        o = er.o;
+        first = (er.rank & kEdgeFirst) != 0;
+        rank = er.rank & (kEdgeFirst - 1);
+        voff = er.voff;
+    }
+    const uint64_t fm = __ballot(first);
+    if (A.write_pattern) {
+        if (first) {
+            A.col_idx[pre_b + rank] = o;
+            A.val_ptr[pre_b + rank] = pre_v + voff;
+        }
+        if (lane == 0) {
+            A.col_idx[pre_b + drank] = c;
+            A.val_ptr[pre_b + drank] = pre_v + dvoff;
+            A.row_ptr[c] = pre_b;
+            A.dof_ptr[c] = pre_d;
+            if (c == m.n_cells - 1) {
+                const int n_tiles = (m.n_cells + kPrepTile - 1) / kPrepTile;
+                const int nblk = 1 + __popcll(fm);
+                A.row_ptr[c + 1] = pre_b + nblk;
+                A.dof_ptr[c + 1] = pre_d + NB;
+                A.val_ptr[pre_b + nblk] = A.tile_off[3 * n_tiles + 1];
+            }
+        }
+    }
+    if (!A.values) return;
+
+    // groups: one per neighbour (led by its first edge) and one per boundary edge
+    const uint64_t gmask = __ballot(first || (lane < nv && o < 0));
+    const int ng = __popcll(gmask);
+    int dupc = 0;  // edges of the row towards this edge's neighbour
+    for (int k = 0; k < nv; ++k) {
+        const int ok = __shfl(o, k, 64);
+        if (ok == o && o >= 0) ++dupc;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) dupc = max(dupc, __shfl_xor(dupc, off, 64));
+
+    const CellGeo g = A.geo[c];
+    RowCtx R;
+    R.bx = box_of(g);
+    R.bx.mx = uniform(R.bx.mx);
+    R.bx.my = uniform(R.bx.my);
+    R.bx.cx = uniform(R.bx.cx);
+    R.bx.cy = uniform(R.bx.cy);
+    R.isq = uniform(1.0 / g.sqrt_box);
+    R.hx = uniform(g.hix - g.lox);
+    R.hy = uniform(g.hiy - g.loy);
+    R.tc = trig_centre(pr, 0.5 * (g.lox + g.hix), 0.5 * (g.loy + g.hiy), 0.5 * sqrt(R.hx * R.hx + R.hy * R.hy));
+    R.tc.x0 = uniform(R.tc.x0);
+    R.tc.y0 = uniform(R.tc.y0);
+    R.tc.sx = uniform(R.tc.sx);
+    R.tc.cx = uniform(R.tc.cx);
+    R.tc.sy = uniform(R.tc.sy);
+    R.tc.cy = uniform(R.tc.cy);
+    R.tc.near = __builtin_amdgcn_readfirstlane(R.tc.near);
+    R.pen_r = uniform(g.abar * P * P / g.h);
+    R.red = A.reduced && A.qr_ok[c];
+    R.QM = R.red ? kQrNodes : (nv - 2) * C::NQT;  // points of the element matrix
+    R.QF0 = (R.QM + FG - 1) / FG * FG;            // edge groups start here
+    R.Qtot = R.QF0 + FG * ng;
+    R.QR = R.red ? (nv - 2) * C::NQT : 0;         // load-only points (reduced rule)
+    R.lane = lane;
+    R.c = c;
+    R.nv = nv;
+    R.vid = vid;
+    R.o = o;
+    R.voff = voff;
+    R.dvoff = dvoff;
+    R.maxdup = max(dupc, 1);
+    R.gmask = gmask;
+    R.ex = ex;
+    R.ey = ey;
+    R.pre_v = pre_v;
+    R.pre_d = pre_d;
+    row_slices<T, P, PN, ADV>(A, R, std::make_integer_sequence<int, C::NSL>{});
+}
+
+template <typename T, int P, int PN>
+static void launch_row(const AsmArgs &a, hipStream_t st) {
+    const bool adv = a.pr.bx != 0.0 || a.pr.by != 0.0 || a.pr.c != 0.0;
+    const int nb = (a.n_rows + 3) / 4;
+    if (nb <= 0) return;
+    if (adv)
+        hipLaunchKernelGGL((k_row2d<T, P, PN, true>), dim3(nb), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_row2d<T, P, PN, false>), dim3(nb), dim3(256), 0, st, a);
+}
+
+bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, hipStream_t st) {
+#define DGP_ROW(T, PP)                                      \
+    if (p == PP) {                                          \
+        if (mixed)                                          \
+            launch_row<T, PP, kMaxP>(a, st);                \
+        else                                                \
+            launch_row<T, PP, PP>(a, st);                   \
+        return true;                                        \
+    }
+    if (precision == 0) {
+        DGP_ROW(double, 1) DGP_ROW(double, 2) DGP_ROW(double, 3) DGP_ROW(double, 4)
+    } else {
+        DGP_ROW(float, 1) DGP_ROW(float, 2) DGP_ROW(float, 3) DGP_ROW(float, 4)
+    }
+#undef DGP_ROW
+    return false;
+}
+
+}  // namespace dgp

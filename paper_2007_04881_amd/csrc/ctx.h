@@ -20,11 +20,12 @@ struct dgp_ctx {
     bool has_mesh = false;
     int dim = 2;
     int64_t n_cells = 0, n_faces = 0, n_vertices = 0, n_cell_vtx = 0;
-    int p_uniform = -1;
+    int p_uniform = -1;                // common degree, or -1 when degrees differ
+    int p_max = 0;
+    int32_t *rows_by_p = nullptr;      // mixed degrees: element ids grouped by degree (stable)
+    int64_t rows_off[dgp::kMaxP + 2] = {};  // group of degree p: rows_by_p[rows_off[p] .. rows_off[p + 1])
     std::vector<void *> mesh_bufs;
     dgp::DevMesh dm{};
-
-    std::vector<int64_t> h_cell_ptr;  // loop offsets, for the assembly chunk partition
 
     // pattern (col_idx / val_ptr sized by the upper bound n_cells + n_cell_vtx)
     bool has_pattern = false;
@@ -36,9 +37,6 @@ struct dgp_ctx {
     dgp::PrepOut prep{};
     int n_tiles = 0;
 
-    // assembly chunk partitions per (precision, p, rule mode)
-    int32_t *chunks[2][dgp::kMaxP + 1][2] = {};
-    int n_chunks[2][dgp::kMaxP + 1][2] = {};
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

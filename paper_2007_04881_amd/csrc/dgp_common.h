@@ -51,11 +51,22 @@ struct alignas(64) CellGeo {
     double area;                // |kappa|
 };
 
+// One loop edge of an element as the assembly needs it (32 bytes).
+struct alignas(16) EdgeRec {
+    double x, y;   // start vertex of the edge
+    int32_t vid;   // its global id (orders the edge's points canonically)
+    int32_t o;     // neighbour across the edge, or minus the boundary code
+    int32_t rank;  // interior edge: position of the neighbour's block in the row (| kEdgeFirst on its first edge)
+    int32_t voff;  // interior edge: value offset of that block inside the row
+};
+constexpr int32_t kEdgeFirst = 1 << 30;
+
 // Outputs of the preparation kernel.
 struct PrepOut {
     CellGeo *geo;        // [n_cells]
     int32_t *nbr;        // [loop entries] neighbour across each edge, or -boundary code
-    int32_t *cnt;        // [n_cells][4] blocks, values, dofs of the row, 0
+    EdgeRec *erec;       // [loop entries]
+    int32_t *cnt;        // [n_cells][4] blocks, values, dofs before the element in its tile; diagonal rank | offset << 8
     int64_t *tile_sum;   // [n_tiles][3]
     int64_t *tile_off;   // [n_tiles + 1][3] exclusive prefix of the tile sums (totals last)
 };
@@ -226,7 +237,7 @@ struct AsmArgs {
     const int32_t *nbr;
     const int32_t *cnt;
     const int64_t *tile_off;
-    const int32_t *chunks;  // [n_chunks + 1][2]: first element, first loop entry
+    const EdgeRec *erec;
     int64_t *row_ptr;
     int32_t *col_idx;
     int64_t *val_ptr;
@@ -239,6 +250,8 @@ struct AsmArgs {
     const double *qr_nodes;  // [n_cells][16][2] (xi, eta) in box coordinates
     const double *qr_w;      // [n_cells][16] weights in box coordinates
     const uint8_t *qr_ok;    // [n_cells]
+    const int32_t *rows;     // rows to assemble (null: all, in order)
+    int32_t n_rows;
 };
 
 }  // namespace dgp

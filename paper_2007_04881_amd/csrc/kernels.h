@@ -11,20 +11,10 @@ namespace dgp {
 // Geometry, edge neighbours and row sizes, then the scan of the tile sums (two launches).
 void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st);
 
-// Capacities of one assembly work-group for (precision, p): the runtime cuts
-// the element rows into chunks of consecutive rows that respect them.
-struct AsmLimits {
-    int slots;               // quadrature tasks
-    int fslots;              // loop edges (face tasks)
-    int maxc;                // elements
-    int tasks_per_triangle;  // element-term tasks per fan sub-triangle
-    int reduced_tasks;       // element-matrix tasks per row with a reduced rule
-};
-void assemble_limits(int precision, int p, AsmLimits *lim);
-
-// Assembly (and pattern) of every block row; p is the common degree of all
-// cells.  Returns false if no kernel is built for (precision, p).
-bool launch_assemble2d(const AsmArgs &a, int n_chunks, int precision, int p, hipStream_t st);
+// One wave per element row: pattern (if a.write_pattern) and values of rows
+// a.rows[0 .. n_rows) (all rows in order if a.rows is null), all of degree p;
+// mixed: neighbours may have any degree up to kMaxP (else all have degree p).
+bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, hipStream_t st);
 
 // ---- reduced volume rules
 void launch_cell_poly(const DevMesh &m, const CellGeo *geo, float *feat, double *mom, double *parea, uint8_t *eligible,

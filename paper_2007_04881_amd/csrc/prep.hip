@@ -6,9 +6,13 @@
 //   discrete ||a||_{L_inf(kappa)} of the penalty, Appendix A);
 // * the neighbour across each edge of the loop (nbr; on the boundary minus the
 //   boundary code: -1 Dirichlet, -2 Neumann);
-// * the size of the element's block row (Section 3.4, Approach 2: one block
-//   per element and per distinct neighbour, however many faces they share):
-//   blocks, values and dofs, and their sums over each tile of 32 elements.
+// * the element's block row (Section 3.4, Approach 2: one block per element
+//   and per distinct neighbour, however many faces they share): for every loop
+//   edge a record with its start vertex, the neighbour, the rank of the
+//   neighbour's block among the row's columns and the block's value offset
+//   inside the row; per element the prefix of blocks, values and dofs inside
+//   its tile of 32 elements and the position of the diagonal block; per tile
+//   the sums.
 // A second, one-work-group kernel scans the tile sums; work-groups never wait
 // on one another (kernel boundaries order the three launches of a step).
 #include "dgp_common.h"
@@ -94,39 +98,50 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
         p = m.cell_p[c];
     }
 
-    // neighbours across this lane's edges (issued first: independent of the geometry chain)
-    int nb[SLOTS], nbsz[SLOTS];
+    // neighbours across this lane's edges and the edges' start vertices
+    int nb[SLOTS], nbsz[SLOTS], code[SLOTS], vq[SLOTS];
+    double xq[SLOTS], yq[SLOTS];
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
         const int f = lane + G * q;
         nb[q] = -1;
         nbsz[q] = 0;
+        code[q] = 0;
+        vq[q] = 0;
+        xq[q] = yq[q] = 0.0;
         if (f < nv) {
             const int F = m.cell_face[s + f];
             const int o = other_cell(m, F, c);
-            out.nbr[s + f] = o >= 0 ? o : -(int)m.face_bc[F];
+            code[q] = o >= 0 ? o : -(int)m.face_bc[F];
+            out.nbr[s + f] = code[q];
             if (o >= 0 && o != c) {
                 nb[q] = o;
                 nbsz[q] = nb2d(m.cell_p[o]);
             }
+            vq[q] = m.cell_vtx[s + f];
+            xq[q] = m.x[vq[q]];
+            yq[q] = m.y[vq[q]];
         }
     }
 
     // ------------------------------------------------------------ geometry
     double lox = 1e300, loy = 1e300, hix = -1e300, hiy = -1e300, a2 = 0.0, d2 = 0.0, amax = -1e300;
-    for (int i = lane; i < nv; i += G) {
-        const int vi = m.cell_vtx[s + i];
-        const double xi = m.x[vi], yi = m.y[vi];
-        lox = fmin(lox, xi);
-        loy = fmin(loy, yi);
-        hix = fmax(hix, xi);
-        hiy = fmax(hiy, yi);
-        const int vn = m.cell_vtx[s + (i + 1 == nv ? 0 : i + 1)];
-        a2 += xi * m.y[vn] - m.x[vn] * yi;
-        for (int j = i + 1; j < nv; ++j) {
-            const int vj = m.cell_vtx[s + j];
-            const double dx = xi - m.x[vj], dy = yi - m.y[vj];
-            d2 = fmax(d2, dx * dx + dy * dy);
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+        const int i = lane + G * q;
+        if (i < nv) {
+            const double xi = xq[q], yi = yq[q];
+            lox = fmin(lox, xi);
+            loy = fmin(loy, yi);
+            hix = fmax(hix, xi);
+            hiy = fmax(hiy, yi);
+            const int vn = m.cell_vtx[s + (i + 1 == nv ? 0 : i + 1)];
+            a2 += xi * m.y[vn] - m.x[vn] * yi;
+            for (int j = i + 1; j < nv; ++j) {
+                const int vj = m.cell_vtx[s + j];
+                const double dx = xi - m.x[vj], dy = yi - m.y[vj];
+                d2 = fmax(d2, dx * dx + dy * dy);
+            }
         }
     }
     if (valid && pr.a1 != 0.0) {
@@ -179,6 +194,49 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     const int my_vals = valid ? nbc * (nbc + szsum) : 0;
     const int my_dofs = valid ? nbc : 0;
 
+    // block ranks and value offsets (columns ascending; the diagonal block is column c)
+    int rank[SLOTS], voff[SLOTS];
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+        rank[q] = nb[q] > c ? 1 : 0;
+        voff[q] = nb[q] > c ? nbc * nbc : 0;
+    }
+    int drank = 0, dvoff = 0;
+#pragma unroll
+    for (int q2 = 0; q2 < SLOTS; ++q2) {
+        for (int l2 = 0; l2 < G; ++l2) {
+            const int v = __shfl(nb[q2], base + l2, 64);
+            const int vf = __shfl((int)first[q2], base + l2, 64);
+            const int vs = __shfl(nbsz[q2], base + l2, 64);
+            if (vf) {
+#pragma unroll
+                for (int q = 0; q < SLOTS; ++q)
+                    if (v < nb[q]) {
+                        rank[q] += 1;
+                        voff[q] += nbc * vs;
+                    }
+                if (v < c) {
+                    drank += 1;
+                    dvoff += nbc * vs;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+        const int f = lane + G * q;
+        if (f < nv) {
+            EdgeRec r;
+            r.x = xq[q];
+            r.y = yq[q];
+            r.vid = vq[q];
+            r.o = code[q];
+            r.rank = nb[q] >= 0 ? (rank[q] | (first[q] ? kEdgeFirst : 0)) : 0;
+            r.voff = nb[q] >= 0 ? voff[q] : 0;
+            out.erec[s + f] = r;
+        }
+    }
+
     if (valid && lane == 0) {
         CellGeo g;
         g.lox = lox;
@@ -190,10 +248,6 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
         g.sqrt_box = sqrt((hix - lox) * (hiy - loy));
         g.area = 0.5 * a2;
         out.geo[c] = g;
-        out.cnt[4 * c + 0] = my_blocks;
-        out.cnt[4 * c + 1] = my_vals;
-        out.cnt[4 * c + 2] = my_dofs;
-        out.cnt[4 * c + 3] = 0;
     }
     if (lane == 0) {
         s_cnt[grp][0] = my_blocks;
@@ -201,6 +255,19 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
         s_cnt[grp][2] = my_dofs;
     }
     __syncthreads();
+    if (valid && lane == 0) {
+        // offsets of the element inside its tile, and where its diagonal block goes
+        int pb = 0, pv = 0, pd = 0;
+        for (int k = 0; k < grp; ++k) {
+            pb += s_cnt[k][0];
+            pv += s_cnt[k][1];
+            pd += s_cnt[k][2];
+        }
+        out.cnt[4 * c + 0] = pb;
+        out.cnt[4 * c + 1] = pv;
+        out.cnt[4 * c + 2] = pd;
+        out.cnt[4 * c + 3] = drank | (dvoff << 8);
+    }
     if (threadIdx.x < 3) {
         int64_t sum = 0;
         for (int k = 0; k < CPB; ++k) sum += s_cnt[k][threadIdx.x];

@@ -42,20 +42,14 @@ static void free_graph(dgp_ctx *c) {
 static void free_mesh(dgp_ctx *c) {
     for (void *p : c->mesh_bufs) (void)hipFree(p);
     c->mesh_bufs.clear();
+    if (c->rows_by_p) (void)hipFree(c->rows_by_p);
+    c->rows_by_p = nullptr;
     for (void *p : {(void *)c->row_ptr, (void *)c->col_idx, (void *)c->val_ptr, (void *)c->dof_ptr, c->work})
         if (p) (void)hipFree(p);
     c->row_ptr = c->val_ptr = c->dof_ptr = nullptr;
     c->col_idx = nullptr;
     c->work = nullptr;
-    for (int q = 0; q < 2; ++q)
-        for (int p = 0; p <= kMaxP; ++p)
-            for (int r = 0; r < 2; ++r) {
-                if (c->chunks[q][p][r]) (void)hipFree(c->chunks[q][p][r]);
-                c->chunks[q][p][r] = nullptr;
-                c->n_chunks[q][p][r] = 0;
-            }
     dgp_free_qrule(c);
-    c->h_cell_ptr.clear();
     c->has_mesh = false;
     free_pattern(c);
     free_graph(c);
@@ -179,6 +173,7 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     ctx->n_vertices = V;
     ctx->n_cell_vtx = nnz_v;
     ctx->p_uniform = pmin == pmax ? pmin : -1;
+    ctx->p_max = pmax;
     DevMesh &d = ctx->dm;
     d.n_cells = (int32_t)N;
     d.n_faces = (int32_t)F;
@@ -206,7 +201,8 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     ctx->n_tiles = (int)((N + kPrepTile - 1) / kPrepTile);
     const size_t o_geo = 0;
     const size_t o_nbr = o_geo + sizeof(CellGeo) * (size_t)N;
-    const size_t o_cnt = o_nbr + ((sizeof(int32_t) * (size_t)nnz_v + 255) & ~size_t(255));
+    const size_t o_erec = o_nbr + ((sizeof(int32_t) * (size_t)nnz_v + 255) & ~size_t(255));
+    const size_t o_cnt = o_erec + ((sizeof(EdgeRec) * (size_t)nnz_v + 255) & ~size_t(255));
     const size_t o_tile = o_cnt + sizeof(int32_t) * 4 * (size_t)N;
     const size_t o_off = o_tile + ((sizeof(int64_t) * 3 * (size_t)ctx->n_tiles + 255) & ~size_t(255));
     const size_t work_bytes = o_off + sizeof(int64_t) * 3 * (size_t)(ctx->n_tiles + 1);
@@ -222,10 +218,24 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     char *b = static_cast<char *>(ctx->work);
     ctx->prep.geo = reinterpret_cast<CellGeo *>(b + o_geo);
     ctx->prep.nbr = reinterpret_cast<int32_t *>(b + o_nbr);
+    ctx->prep.erec = reinterpret_cast<EdgeRec *>(b + o_erec);
     ctx->prep.cnt = reinterpret_cast<int32_t *>(b + o_cnt);
     ctx->prep.tile_sum = reinterpret_cast<int64_t *>(b + o_tile);
     ctx->prep.tile_off = reinterpret_cast<int64_t *>(b + o_off);
-    ctx->h_cell_ptr.assign(m->cell_ptr, m->cell_ptr + N + 1);
+    if (pmin != pmax) {
+        // mixed degrees: one launch per degree over the elements of that degree (in id order)
+        std::vector<int32_t> rows((size_t)N);
+        int64_t cnt[kMaxP + 2] = {};
+        for (int64_t c = 0; c < N; ++c) cnt[m->cell_p[c] + 1] += 1;
+        for (int p = 1; p <= kMaxP + 1; ++p) cnt[p] += cnt[p - 1];
+        for (int p = 0; p <= kMaxP + 1; ++p) ctx->rows_off[p] = cnt[p];
+        for (int64_t c = 0; c < N; ++c) rows[(size_t)cnt[m->cell_p[c]]++] = (int32_t)c;
+        if (hipMalloc(&ctx->rows_by_p, sizeof(int32_t) * (size_t)N) != hipSuccess) {
+            free_mesh(ctx);
+            return fail(ctx, DGP_ENOMEM, "row groups");
+        }
+        HIPCHK(ctx, hipMemcpy(ctx->rows_by_p, rows.data(), sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice));
+    }
     ctx->has_mesh = true;
     return DGP_OK;
 }
@@ -237,7 +247,6 @@ static DevProblem neutral_problem() {
     return d;
 }
 
-static dgp_status prepare_chunks(dgp_ctx *ctx, int precision, int p, int rule_mode);
 static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
                                int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed);
 
@@ -247,12 +256,7 @@ dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
     HIPCHK(ctx, hipSetDevice(ctx->device));
     free_pattern(ctx);
     free_graph(ctx);
-    const int p = ctx->p_uniform;
-    if (p < 1 || p > 3)
-        return fail(ctx, DGP_EUNSUPPORTED, "this version assembles meshes of one common degree p in 1..3");
-    dgp_status st = prepare_chunks(ctx, DGP_F64, p, DGP_RULE_PLAIN);
-    if (st) return st;
-    st = enqueue_step(ctx, neutral_problem(), DGP_F64, DGP_RULE_PLAIN, 0, 1, nullptr, nullptr, ctx->stream, false);
+    dgp_status st = enqueue_step(ctx, neutral_problem(), DGP_F64, DGP_RULE_PLAIN, 0, 1, nullptr, nullptr, ctx->stream, false);
     if (st) return st;
     int64_t tot[3];
     HIPCHK(ctx, hipMemcpyAsync(tot, ctx->prep.tile_off + 3 * ctx->n_tiles, sizeof(tot), hipMemcpyDeviceToHost,
@@ -305,58 +309,20 @@ static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int
     if (precision != DGP_F64 && precision != DGP_F32) return fail(ctx, DGP_EINVAL, "precision %d", precision);
     if (prob->u_kind != DGP_U_SIN && prob->u_kind != DGP_U_POLY) return fail(ctx, DGP_EINVAL, "u_kind");
     if (!(prob->c_sigma >= 0.0)) return fail(ctx, DGP_EINVAL, "c_sigma must be >= 0");
-    if (ctx->p_uniform < 1 || ctx->p_uniform > 3)
-        return fail(ctx, DGP_EUNSUPPORTED, "this version assembles meshes of one common degree p in 1..3");
     if (rule_mode != DGP_RULE_PLAIN && rule_mode != DGP_RULE_REDUCED)
         return fail(ctx, DGP_EINVAL, "rule_mode %d", rule_mode);
     if (rule_mode == DGP_RULE_REDUCED) {
         if (!ctx->has_qrule) return fail(ctx, DGP_ESTATE, "reduced rules requested before dgp_qrule_build");
         if (prob->a1 != 0.0)
             return fail(ctx, DGP_EINVAL, "reduced rules integrate polynomials of degree <= 6: a must be constant");
-        if (ctx->p_uniform > 3) return fail(ctx, DGP_EUNSUPPORTED, "reduced rules need p <= 3");
+        if (ctx->p_max > 3) return fail(ctx, DGP_EUNSUPPORTED, "reduced rules need p <= 3");
     }
-    return prepare_chunks(ctx, precision, ctx->p_uniform, rule_mode);
-}
-
-// Cut the rows into chunks of consecutive rows whose quadrature tasks, loop
-// edges and elements fit one assembly work-group.  The table holds, per
-// chunk, its first element and its first loop entry (plus a sentinel).
-static dgp_status prepare_chunks(dgp_ctx *ctx, int precision, int p, int rule_mode) {
-    if (ctx->chunks[precision][p][rule_mode]) return DGP_OK;
-    AsmLimits lim;
-    assemble_limits(precision, p, &lim);
-    if (lim.slots == 0) return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
-    std::vector<int32_t> tab{0, 0};
-    int tasks = 0, faces = 0, cells = 0;
-    for (int64_t c = 0; c < ctx->n_cells; ++c) {
-        const int nv = (int)(ctx->h_cell_ptr[c + 1] - ctx->h_cell_ptr[c]);
-        const int t = (nv - 2) * lim.tasks_per_triangle + nv + (rule_mode ? lim.reduced_tasks : 0);
-        if (t > lim.slots || nv > lim.fslots)
-            return fail(ctx, DGP_EUNSUPPORTED, "cell %lld is too large for one work-group", (long long)c);
-        if (tasks + t > lim.slots || faces + nv > lim.fslots || cells + 1 > lim.maxc) {
-            tab.push_back((int32_t)c);
-            tab.push_back((int32_t)ctx->h_cell_ptr[c]);
-            tasks = faces = cells = 0;
-        }
-        tasks += t;
-        faces += nv;
-        cells += 1;
-    }
-    tab.push_back((int32_t)ctx->n_cells);
-    tab.push_back((int32_t)ctx->h_cell_ptr[ctx->n_cells]);
-    int32_t *d = nullptr;
-    if (hipMalloc(&d, sizeof(int32_t) * tab.size()) != hipSuccess)
-        return fail(ctx, DGP_ENOMEM, "chunk table allocation failed");
-    HIPCHK(ctx, hipMemcpy(d, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice));
-    ctx->chunks[precision][p][rule_mode] = d;
-    ctx->n_chunks[precision][p][rule_mode] = (int)tab.size() / 2 - 1;
     return DGP_OK;
 }
 
 // One step: preparation kernel, then the assembly kernel (values = 0: pattern only).
 static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
                                int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed) {
-    const int p = ctx->p_uniform;
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
     launch_prep(ctx->dm, dp, ctx->prep, st);
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
@@ -367,7 +333,9 @@ static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision
     a.nbr = ctx->prep.nbr;
     a.cnt = ctx->prep.cnt;
     a.tile_off = ctx->prep.tile_off;
-    a.chunks = ctx->chunks[precision][p][rule_mode];
+    a.erec = ctx->prep.erec;
+    a.rows = nullptr;
+    a.n_rows = (int32_t)ctx->n_cells;
     a.row_ptr = ctx->row_ptr;
     a.col_idx = ctx->col_idx;
     a.val_ptr = ctx->val_ptr;
@@ -380,8 +348,19 @@ static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision
     a.qr_nodes = ctx->qr_nodes;
     a.qr_w = ctx->qr_w;
     a.qr_ok = ctx->qr_ok;
-    if (!launch_assemble2d(a, ctx->n_chunks[precision][p][rule_mode], precision, p, st))
-        return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
+    if (ctx->p_uniform > 0) {
+        if (!launch_row2d(a, precision, ctx->p_uniform, false, st))
+            return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, ctx->p_uniform);
+    } else {
+        for (int p = 1; p <= kMaxP; ++p) {
+            const int64_t n = ctx->rows_off[p + 1] - ctx->rows_off[p];
+            if (n == 0) continue;
+            a.rows = ctx->rows_by_p + ctx->rows_off[p];
+            a.n_rows = (int32_t)n;
+            if (!launch_row2d(a, precision, p, true, st))
+                return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
+        }
+    }
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[2], st));
     HIPCHK(ctx, hipGetLastError());
     ctx->ev_pattern = timed;

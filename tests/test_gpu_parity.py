@@ -45,12 +45,46 @@ def test_workload2_full_size(precision):
     _case(config_mesh(2), problem_params(2), precision)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_voronoi_degrees(p, precision):
     # 1000 cells: 32 rows per FP32 work-group -> a ragged last work-group
     m = voronoi_mesh(1000, 77, lloyd=1, p=p)
     _case(m, DAR, precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mixed_degrees(precision):
+    # degrees drawn from {1, 2, 3, 4}: one launch per degree, cross blocks n_b(p) x n_b(p')
+    m = voronoi_mesh(1000, 79, lloyd=1, p=1)
+    m = m.with_degrees(np.random.default_rng(7).integers(1, 5, m.n_cells))
+    _case(m, DAR, precision)
+    _case(m, POLY, precision, full_path=True)
+
+
+def _sampled_case(mesh, params, precision, n_sample=400):
+    """Full-size run in the benchmark's launch configuration; the pattern is
+    compared in full, values on sampled rows (the first, the last, random)."""
+    print(f"[case] {mesh.name} cells={mesh.n_cells} prec={precision} sampled", flush=True)
+    pat = oracle.pattern(mesh)
+    g = gpu_assemble(mesh, params, precision, full_path=True)
+    check_pattern(g, pat)
+    rng = np.random.default_rng(11)
+    rows = np.unique(np.concatenate([[0, mesh.n_cells - 1], rng.integers(0, mesh.n_cells, n_sample)]))
+    vals, rhs = oracle.assemble(mesh, oracle_problem(params), rows=rows, pat=pat)
+    eb, er = block_errors(g, vals, rhs, pat, rows=rows)
+    print(f"       worst block {eb:.3e}  worst rhs row {er:.3e} over {len(rows)} rows", flush=True)
+    assert eb <= TOL[precision], eb
+    assert er <= TOL[precision], er
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_workload3_mixed_degrees_full_size(precision):
+    _sampled_case(config_mesh(3), problem_params(3), precision)
+
+
+def test_workload5_p3_full_size():
+    _sampled_case(config_mesh(5), problem_params(5), 1)
 
 
 @pytest.mark.parametrize("precision", [0, 1])

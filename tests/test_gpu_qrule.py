@@ -185,6 +185,37 @@ def test_reduced_assembly_matches_plain_oracle(p, params, precision):
     ctx.close()
 
 
+def test_reduced_assembly_full_size_sampled():
+    """The 262,144-cell p = 3 workload with template-initialised rules, FP32,
+    sampled rows against the oracle's plain assembly."""
+    import torch
+    import paper_2007_04881_amd as D
+    from meshgen import config_mesh, problem_params
+    m = config_mesh(5)
+    params = problem_params(5)
+    print(f"[case] reduced assembly, {m.n_cells} cells", flush=True)
+    ctx = _ctx()
+    ctx.upload(m)
+    ctx.pattern()
+    st = ctx.qrule_build(D.INIT_TEMPLATE, 8, 1e-10)
+    assert st.n_accepted >= 0.99 * st.n_eligible
+    vals, rhs = ctx.outputs(D.F32)
+    ctx.assemble(params, D.F32, vals, rhs, rule_mode=D.RULE_REDUCED)
+    rp, ci, vp, dp = ctx.pattern_tensors()
+    torch.cuda.synchronize()
+    g = dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val_ptr=vp.cpu().numpy(),
+             dof_ptr=dp.cpu().numpy(), vals=vals.double().cpu().numpy(), rhs=rhs.double().cpu().numpy(),
+             info=(ctx.info.n_rows, ctx.info.nnzb, ctx.info.n_vals, ctx.info.n_dofs))
+    ctx.close()
+    pat = oracle.pattern(m)
+    check_pattern(g, pat)
+    rows = np.unique(np.concatenate([[0, m.n_cells - 1], np.random.default_rng(12).integers(0, m.n_cells, 300)]))
+    ov, orhs = oracle.assemble(m, oracle_problem(params), rows=rows, pat=pat)
+    eb, er = block_errors(g, ov, orhs, pat, rows=rows)
+    print(f"       worst block {eb:.3e}  worst rhs row {er:.3e} over {len(rows)} rows", flush=True)
+    assert eb <= 1e-5 and er <= 1e-5
+
+
 def test_training_lowers_the_loss_and_network_rules_are_accepted():
     import paper_2007_04881_amd as D
     print("[case] training 20000 polygons x 4 epochs", flush=True)
