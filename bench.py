@@ -24,6 +24,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+KERNEL_SOURCES = ["assemble_row.hip", "asm_common.h", "dgp_common.h", "rules_data.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_row2d_p2_f32_voronoi16384.json")
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2007_04881_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the assembly kernel from the committed counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size), or None if
+    the kernel sources changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -223,8 +250,8 @@ def main():
         "single_shot_ms": single_ms,
         "kernel_ms": avg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_assemble2d<float,2>", "algorithmic_bytes": abytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "k_row2d<float,2,2,true>", "algorithmic_bytes": abytes},
     }
     ctx.close()
     if not args.no_reduced:

@@ -65,8 +65,48 @@ struct RowCfg {
     static constexpr int NQT = Tri<TDEG>::n;
 };
 
+// Cross-lane moves.  DPP patterns (quad_perm xor 1 / xor 2, half-row and row
+// mirrors) pair lanes inside rows of 16; v_permlane16_swap / v_permlane32_swap
+// exchange whole rows / halves of the wave between two registers.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+// lo <- lo + hi of the partner half (O = 32) or row (O = 16): after the swap the
+// two registers hold, on every lane, the two addends of the lane's kept half
+template <int O>
+__device__ __forceinline__ float swap_add(float lo, float hi) {
+    const auto r = O == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false)
+                           : __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <int O>
+__device__ __forceinline__ double swap_add(double lo, double hi) {
+    const long long a = __double_as_longlong(lo), b = __double_as_longlong(hi);
+    const unsigned a0 = (unsigned)(a & 0xffffffffLL), a1 = (unsigned)(a >> 32);
+    const unsigned b0 = (unsigned)(b & 0xffffffffLL), b1 = (unsigned)(b >> 32);
+    const auto r0 = O == 32 ? __builtin_amdgcn_permlane32_swap(a0, b0, false, false)
+                            : __builtin_amdgcn_permlane16_swap(a0, b0, false, false);
+    const auto r1 = O == 32 ? __builtin_amdgcn_permlane32_swap(a1, b1, false, false)
+                            : __builtin_amdgcn_permlane16_swap(a1, b1, false, false);
+    const double x = __longlong_as_double(((long long)r1[0] << 32) | r0[0]);
+    const double y = __longlong_as_double(((long long)r1[1] << 32) | r0[1]);
+    return x + y;
+}
+
 // Reduce-scatter over the 64 lanes: on return a[0] of lane l is the sum over
-// lanes of entry l.  EC = entries that may be nonzero (a[EC..] are zero).
+// lanes of entry l.  EC = entries that may be nonzero (a[EC..] are zero).  The
+// stage of order O pairs lanes that differ in bit log2(O) (and possibly lower
+// bits); each keeps the half of its live entries selected by that bit.
 template <typename T, int O, int EC>
 struct WaveRS {
     __device__ static __forceinline__ void run(T (&a)[64], int lane) {
@@ -76,9 +116,14 @@ struct WaveRS {
         for (int k = 0; k < NP; ++k) {
             const T lo = a[k];
             const T hi = (k + O < EC) ? a[k + O] : T(0);
-            const T send = up ? lo : hi;
-            const T keep = up ? hi : lo;
-            a[k] = keep + __shfl_xor(send, O, 64);
+            if (O >= 16) {
+                a[k] = swap_add<(O >= 16 ? O : 16)>(lo, hi);
+            } else {
+                const T send = up ? lo : hi;
+                const T keep = up ? hi : lo;
+                constexpr int CTRL = O == 8 ? kDppMirror : O == 4 ? kDppHalfMirror : O == 2 ? kDppXor2 : kDppXor1;
+                a[k] = keep + dpp<CTRL>(send);
+            }
         }
         WaveRS<T, O / 2, (O < EC ? O : EC)>::run(a, lane);
     }
@@ -87,6 +132,15 @@ template <typename T, int EC>
 struct WaveRS<T, 0, EC> {
     __device__ static __forceinline__ void run(T (&)[64], int) {}
 };
+
+// sum over an aligned group of FG (4 or 8) lanes, result in every lane of the group
+template <int FG, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+    v += dpp<kDppXor1>(v);
+    v += dpp<kDppXor2>(v);
+    if (FG == 8) v += dpp<kDppHalfMirror>(v);
+    return v;
+}
 
 // A wave-uniform double moved to scalar registers.
 __device__ __forceinline__ double uniform(double v) {
@@ -118,7 +172,7 @@ struct RowCtx {
     TrigCentre tc;
 };
 
-template <typename T, int P, int PN, bool ADV, int SL>
+template <typename T, int P, int PN, bool MX, bool ADV, int SL>
 __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
     using C = RowCfg<T, P, PN>;
     constexpr int NB = C::NB, JS = C::JS, FG = C::FG, ED = C::ED;
@@ -155,7 +209,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
         int po = P;  // degree across the edge (the row's own on the boundary)
         if (cross) {
             go = A.geo[og];
-            po = PN == P ? P : m.cell_p[og];
+            po = MX ? (int)m.cell_p[og] : P;
             pen_o = go.abar * po * po / go.h;
         }
         const int nbo = nb2d(po);
@@ -312,9 +366,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
 #pragma unroll
                         for (int i = 0; i < NB; ++i) col[i] = fmat(ev.g0[i], u0, fmat(ev.g1[i], u1, ev.v[i] * u2));
 #pragma unroll
-                        for (int off = 1; off < FG; off <<= 1)
-#pragma unroll
-                            for (int i = 0; i < NB; ++i) col[i] += __shfl_xor(col[i], off, 64);
+                        for (int i = 0; i < NB; ++i) col[i] = group_sum<FG>(col[i]);
                         if (wr) {
 #pragma unroll
                             for (int i = 0; i < NB; ++i)
@@ -365,14 +417,15 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
     }
 }
 
-template <typename T, int P, int PN, bool ADV, int... SL>
+template <typename T, int P, int PN, bool MX, bool ADV, int... SL>
 __device__ __forceinline__ void row_slices(const AsmArgs &A, const RowCtx &R, std::integer_sequence<int, SL...>) {
-    (row_slice<T, P, PN, ADV, SL>(A, R), ...);
+    (row_slice<T, P, PN, MX, ADV, SL>(A, R), ...);
 }
 
 }  // namespace
 
-template <typename T, int P, int PN, bool ADV>
+// MX: neighbours may have other degrees than P (up to PN); otherwise all have degree P = PN
+template <typename T, int P, int PN, bool MX, bool ADV>
 __global__ void __launch_bounds__(256) k_row2d(AsmArgs A) {
     using C = RowCfg<T, P, PN>;
     constexpr int NB = C::NB, FG = C::FG;
@@ -478,27 +531,27 @@ __global__ void __launch_bounds__(256) k_row2d(AsmArgs A) {
     R.ey = ey;
     R.pre_v = pre_v;
     R.pre_d = pre_d;
-    row_slices<T, P, PN, ADV>(A, R, std::make_integer_sequence<int, C::NSL>{});
+    row_slices<T, P, PN, MX, ADV>(A, R, std::make_integer_sequence<int, C::NSL>{});
 }
 
-template <typename T, int P, int PN>
+template <typename T, int P, int PN, bool MX>
 static void launch_row(const AsmArgs &a, hipStream_t st) {
     const bool adv = a.pr.bx != 0.0 || a.pr.by != 0.0 || a.pr.c != 0.0;
     const int nb = (a.n_rows + 3) / 4;
     if (nb <= 0) return;
     if (adv)
-        hipLaunchKernelGGL((k_row2d<T, P, PN, true>), dim3(nb), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_row2d<T, P, PN, MX, true>), dim3(nb), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((k_row2d<T, P, PN, false>), dim3(nb), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_row2d<T, P, PN, MX, false>), dim3(nb), dim3(256), 0, st, a);
 }
 
 bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, hipStream_t st) {
 #define DGP_ROW(T, PP)                                      \
     if (p == PP) {                                          \
         if (mixed)                                          \
-            launch_row<T, PP, kMaxP>(a, st);                \
+            launch_row<T, PP, kMaxP, true>(a, st);          \
         else                                                \
-            launch_row<T, PP, PP>(a, st);                   \
+            launch_row<T, PP, PP, false>(a, st);            \
         return true;                                        \
     }
     if (precision == 0) {

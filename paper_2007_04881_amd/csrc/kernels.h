@@ -40,6 +40,8 @@ struct GemmArgs {
     int act;            // 0 identity, 1 SiLU (pre-activation to Zout if set), 2 times SiLU'(Z)
     const float *Z;     // act 2: pre-activation, leading dimension ldc
     float *Zout;
+    float *work;        // split-K partial sums, at least ksplit * M * N floats (ksplit > 1)
+    int ksplit;         // K ranges summed separately, then added in a fixed order
 };
 void launch_gemm(const GemmArgs &g, hipStream_t st);
 // forward pass of the network over n rows of x [n][36]; h1, h2 [n][128] scratch; out [n][48]

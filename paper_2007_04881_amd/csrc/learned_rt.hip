@@ -72,19 +72,34 @@ GemmArgs gemm(const float *A, int64_t sam, int64_t sak, const float *B, int64_t 
     g.M = (int)M;
     g.N = N;
     g.K = K;
+    g.ksplit = 1;
+    return g;
+}
+
+// weight gradients: K is the batch, M x N at most 128 x 128, so the product is
+// split over K to occupy the device (partials summed in a fixed order)
+constexpr int kSplitK = 32;
+GemmArgs gemm_wgrad(const float *A, int64_t sak, const float *B, int64_t sbk, float *C, int64_t ldc, int M, int N,
+                    int K, float *work) {
+    GemmArgs g = gemm(A, 1, sak, B, sbk, 1, C, ldc, M, N, K);
+    g.work = work;
+    g.ksplit = K >= 64 * kSplitK ? kSplitK : (K >= 1024 ? K / 64 : 1);
     return g;
 }
 
 // Activations and gradients of one batch of at most `rows` rows.
 struct Workspace {
     DevBuf buf;
-    float *Z[3], *H[3], *O, *dO, *dA, *dB, *loss;
+    float *Z[3], *H[3], *O, *dO, *dA, *dB, *loss, *split;
     int64_t rows = 0;
     bool alloc(int64_t r) {
         rows = r;
         const size_t h = (size_t)r * kQrHidden, o = (size_t)r * kQrOut;
-        if (!buf.alloc(sizeof(float) * (8 * h + 2 * o + (size_t)r + 64))) return false;
+        const size_t sp = (size_t)kSplitK * kQrHidden * kQrHidden;
+        if (!buf.alloc(sizeof(float) * (8 * h + 2 * o + (size_t)r + 64 + sp))) return false;
         float *p = buf.as<float>();
+        split = p;
+        p += sp;
         for (int i = 0; i < 3; ++i) {
             Z[i] = p;
             p += h;
@@ -124,7 +139,8 @@ void train_step(const float *P, const float *x, const double *mom, const double 
     launch_gemm(g, st);
     launch_loss_grad(w.O, mom, area, n, n, w.dO, loss_rows, st);
     // output layer
-    launch_gemm(gemm(w.H[2], 1, kQrHidden, w.dO, kQrOut, 1, grad + kMlpW4, kQrOut, kQrHidden, kQrOut, (int)n), st);
+    launch_gemm(gemm_wgrad(w.H[2], kQrHidden, w.dO, kQrOut, grad + kMlpW4, kQrOut, kQrHidden, kQrOut, (int)n, w.split),
+                st);
     launch_colsum(w.dO, n, kQrOut, grad + kMlpB4, st);
     g = gemm(w.dO, kQrOut, 1, P + kMlpW4, 1, kQrOut, w.dA, kQrHidden, n, kQrHidden, kQrOut);
     g.act = 2;
@@ -133,7 +149,8 @@ void train_step(const float *P, const float *x, const double *mom, const double 
     // hidden layers 3, 2, 1: dA holds dL/dZ_l on entry
     float *dz = w.dA, *dn = w.dB;
     for (int l = 2; l >= 0; --l) {
-        launch_gemm(gemm(in[l], 1, kin[l], dz, kQrHidden, 1, grad + wo[l], kQrHidden, kin[l], kQrHidden, (int)n), st);
+        launch_gemm(gemm_wgrad(in[l], kin[l], dz, kQrHidden, grad + wo[l], kQrHidden, kin[l], kQrHidden, (int)n, w.split),
+                    st);
         launch_colsum(dz, n, kQrHidden, grad + bo[l], st);
         if (l > 0) {
             g = gemm(dz, kQrHidden, 1, P + wo[l], 1, kQrHidden, dn, kQrHidden, n, kQrHidden, kQrHidden);

@@ -38,17 +38,20 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
     const bool a_kfast = g.sak == 1, b_nfast = g.sbn == 1;
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    // this work-group's K range (split-K: blockIdx.z of ksplit, in multiples of TK)
+    const int kchunk = (g.K + g.ksplit * TK - 1) / (g.ksplit * TK) * TK;
+    const int kbeg = blockIdx.z * kchunk, kend = min(g.K, kbeg + kchunk);
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
         for (int e = tid; e < TM * TK; e += 256) {
             const int mm = a_kfast ? e / TK : e % TM, kk = a_kfast ? e % TK : e / TM;
             const int64_t gm = m0 + mm;
             const int gk = k0 + kk;
-            As[kk][mm] = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + (int64_t)gk * g.sak] : 0.0f;
+            As[kk][mm] = (gm < g.M && gk < kend) ? g.A[gm * g.sam + (int64_t)gk * g.sak] : 0.0f;
         }
         for (int e = tid; e < TK * TN; e += 256) {
             const int nn = b_nfast ? e % TN : e / TK, kk = b_nfast ? e / TN : e % TK;
             const int gn = n0 + nn, gk = k0 + kk;
-            Bs[kk][nn] = (gn < g.N && gk < g.K) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.0f;
+            Bs[kk][nn] = (gn < g.N && gk < kend) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.0f;
         }
         __syncthreads();
 #pragma unroll
@@ -63,6 +66,15 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     // accumulator r of lane l holds C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
     const int gn = n0 + wn * 32 + (lane & 31);
     if (gn >= g.N) return;
+    if (g.ksplit > 1) {
+        float *part = g.work + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t gm = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (gm < g.M) part[gm * g.N + gn] = acc[r];
+        }
+        return;
+    }
     const float bias = g.bias ? g.bias[gn] : 0.0f;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -80,10 +92,35 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
 }
 
-void launch_gemm(const GemmArgs &g, hipStream_t st) {
-    if (g.M <= 0 || g.N <= 0) return;
-    dim3 grid((unsigned)((g.M + TM - 1) / TM), (unsigned)((g.N + TN - 1) / TN));
+// Split-K epilogue: C = epi(sum over the ksplit partial products, in order).
+__global__ void k_splitk_sum(GemmArgs g) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)g.M * g.N) return;
+    const int64_t m = e / g.N;
+    const int n = (int)(e - m * g.N);
+    float v = 0.0f;
+    for (int z = 0; z < g.ksplit; ++z) v += g.work[(int64_t)z * g.M * g.N + e];
+    if (g.bias) v += g.bias[n];
+    if (g.act == 1) {
+        if (g.Zout) g.Zout[m * g.ldc + n] = v;
+        v = silu(v);
+    } else if (g.act == 2) {
+        v *= dsilu(g.Z[m * g.ldc + n]);
+    }
+    g.C[m * g.ldc + n] = v;
+}
+
+void launch_gemm(const GemmArgs &g0, hipStream_t st) {
+    if (g0.M <= 0 || g0.N <= 0) return;
+    GemmArgs g = g0;
+    dim3 grid((unsigned)((g.M + TM - 1) / TM), (unsigned)((g.N + TN - 1) / TN), 1);
+    if (g.ksplit < 1 || !g.work) g.ksplit = 1;
+    grid.z = (unsigned)g.ksplit;
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+    if (g.ksplit > 1) {
+        const int64_t n = (int64_t)g.M * g.N;
+        hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g);
+    }
 }
 
 static GemmArgs dense(const float *x, int64_t n, int k_in, const float *W, const float *b, int n_out, float *y,

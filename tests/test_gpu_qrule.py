@@ -121,8 +121,9 @@ def test_network_forward_matches_oracle():
 
 def test_loss_gradient_and_adam_match_oracle():
     import torch
-    print("[case] loss gradient, 517 rows", flush=True)
-    polys = [L.random_polygon(i, 8) for i in range(517)]
+    # 2,100 rows: the weight gradients take the split-K path (partials summed in order)
+    print("[case] loss gradient, 2100 rows", flush=True)
+    polys = [L.random_polygon(i, 8) for i in range(2100)]
     X = np.stack([L.features(v) for v in polys]).astype(np.float32).astype(np.float64)
     A = np.array([L.polygon_area(v) for v in polys])
     M = np.stack([L.polygon_moments(v) for v in polys])
