@@ -65,6 +65,10 @@ __device__ __forceinline__ Box box_of(const CellGeo &g) {
 }
 
 // sqrt((2a+1)(2b+1)) of basis function i: its normalisation times sqrt(|B|)
+// the same as compile-time constants (for unrolled indices)
+constexpr double kNorm[15] = {1.0, 1.7320508075688772, 1.7320508075688772, 2.23606797749979, 3.0,
+                              2.23606797749979, 2.6457513110645907, 3.872983346207417, 3.872983346207417,
+                              2.6457513110645907, 3.0, 4.58257569495584, 5.0, 4.58257569495584, 3.0};
 static __constant__ double c_norm[15] = {1.0, 1.7320508075688772, 1.7320508075688772, 2.23606797749979, 3.0,
                                   2.23606797749979, 2.6457513110645907, 3.872983346207417, 3.872983346207417,
                                   2.6457513110645907, 3.0, 4.58257569495584, 5.0, 4.58257569495584, 3.0};

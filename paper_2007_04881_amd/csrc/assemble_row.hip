@@ -63,6 +63,9 @@ struct RowCfg {
     static constexpr int FG = NG <= 4 ? 4 : 8;         // lanes per edge group
     static constexpr int TDEG = P <= 2 ? 4 : 2 * P;
     static constexpr int NQT = Tri<TDEG>::n;
+    // waves per SIMD the register allocation must allow (measured: three waves
+    // beat two for the FP32 p <= 2 kernels even with a small spill)
+    static constexpr int MINW = (sizeof(T) == 4 && P <= 2 && PN <= 2) ? 3 : 1;
 };
 
 // Cross-lane moves.  DPP patterns (quad_perm xor 1 / xor 2, half-row and row
@@ -142,6 +145,13 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // A wave-uniform double moved to scalar registers.
 __device__ __forceinline__ double uniform(double v) {
     const long long b = __double_as_longlong(v);
@@ -151,22 +161,26 @@ __device__ __forceinline__ double uniform(double v) {
 }
 
 // Per-point coefficients of the rank-3 updates (see the file comment).
+// The cross block reuses the edge's own coefficients: s_0 = -b0 v', s_1 = -b1 v',
+// s_2 = x0 g0' + x1 g1' - c2 v' (lanes of element points or boundary edges
+// form cross terms too, but their groups are never written).
 template <typename T>
 struct PointCoef {
     T a0, b0, a1, b1, c0, c1, c2;  // element block
-    T s0, s1, x0, x1, x2;          // cross block: s_0 = s0 v', s_1 = s1 v', s_2 = x0 g0' + x1 g1' + x2 v'
+    T x0, x1;                      // cross block (neighbour's box factors)
     T r0, r1, r2;                  // load
     __device__ __forceinline__ void zero() {
-        a0 = b0 = a1 = b1 = c0 = c1 = c2 = s0 = s1 = x0 = x1 = x2 = r0 = r1 = r2 = T(0);
+        a0 = b0 = a1 = b1 = c0 = c1 = c2 = x0 = x1 = r0 = r1 = r2 = T(0);
     }
 };
 
 // Everything a slice of the row needs, computed once per row.
 struct RowCtx {
     int lane, c, nv, vid, o, voff, dvoff, maxdup, QM, QF0, Qtot, QR;
+    int gtab;  // lane g < number of groups: loop index of the g-th group's leading edge
     bool red;
     uint64_t gmask;
-    double ex, ey, isq, hx, hy, pen_r;
+    double ex, ey, x0, y0, isq, hx, hy, pen_r;  // x0, y0: the fan apex (first vertex)
     int64_t pre_v, pre_d;
     Box bx;
     TrigCentre tc;
@@ -198,23 +212,22 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
         const int gi = edge_lane ? (q - QF0) / FG : 0;
         const int gq = edge_lane ? (q - QF0) - gi * FG : 0;
         // leader edge of the lane's group
-        int fl = 0;
-        for (int k = 0; k < nv; ++k)
-            if (((R.gmask >> k) & 1ull) && __popcll(R.gmask & ((1ull << k) - 1ull)) == gi) fl = k;
+        const int fl = __shfl(R.gtab, gi, 64);
         const int og = __shfl(o, fl, 64);
         const int gvoff = __shfl(voff, fl, 64);
         const bool cross = edge_lane && og >= 0;
-        CellGeo go{};
-        double pen_o = 0.0;
+        Box bo{0.0, 0.0, 0.0, 0.0};
+        double pen_o = 0.0, xsc = 0.0;
         int po = P;  // degree across the edge (the row's own on the boundary)
         if (cross) {
-            go = A.geo[og];
+            const CellGeo go = A.geo[og];
+            bo = box_of(go);
             po = MX ? (int)m.cell_p[og] : P;
             pen_o = go.abar * po * po / go.h;
+            xsc = R.isq / go.sqrt_box;
         }
         const int nbo = nb2d(po);
         const int ngf = (P > po ? P : po) + 1 > 3 ? (P > po ? P : po) + 1 : 3;  // this edge's Gauss points
-        const double xsc = cross ? R.isq / go.sqrt_box : 0.0;
         const bool pass_has_edges = base + 64 > QF0 && base < Qtot;
 
         for (int d = 0; d < R.maxdup; ++d) {
@@ -236,7 +249,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             const int tri = vol && !R.red ? q / C::NQT : 0;
             const int s1 = vol ? tri + 1 : (fk >= 0 ? fk : 0);
             const int s2 = vol ? tri + 2 : (fk >= 0 ? (fk + 1 == nv ? 0 : fk + 1) : 0);
-            const double X0 = __shfl(ex, 0, 64), Y0 = __shfl(ey, 0, 64);
+            const double X0 = R.x0, Y0 = R.y0;
             const double X1 = __shfl(ex, s1, 64), Y1 = __shfl(ey, s1, 64);
             const double X2 = __shfl(ex, s2, 64), Y2 = __shfl(ey, s2, 64);
             const int V1 = __shfl(vid, s1, 64), V2 = __shfl(vid, s2, 64);
@@ -291,7 +304,6 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                 xi = (px - bx.mx) * bx.cx;
                 eta = (py - bx.my) * bx.cy;
                 if (og >= 0) {
-                    const Box bo = box_of(go);
                     const double sigma = pr.c_sigma * (R.pen_r > pen_o ? R.pen_r : pen_o);
                     const double ha = -0.5 * w * coef_a_near(pr, tc, px, py), hs = (sigma - up) * w;
                     pc.b0 = T(ha * cnx);
@@ -299,11 +311,8 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                     pc.c0 = T(ha * cnx);
                     pc.c1 = T(ha * cny);
                     pc.c2 = T(hs);
-                    pc.s0 = T(-ha * cnx);
-                    pc.s1 = T(-ha * cny);
                     pc.x0 = T(ha * bo.cx * nx);
                     pc.x1 = T(ha * bo.cy * ny);
-                    pc.x2 = T(-hs);
                     xin = (px - bo.mx) * bo.cx;
                     etan = (py - bo.my) * bo.cy;
                 } else if (og == -1) {
@@ -360,18 +369,19 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                     if (j < C::NBN && j < nbo) {
                         const T vj = Lx[exp_a(j)] * Ly[exp_b(j)];
                         const T gj0 = dLx[exp_a(j)] * Ly[exp_b(j)], gj1 = Lx[exp_a(j)] * dLy[exp_b(j)];
-                        const T u0 = pc.s0 * vj, u1 = pc.s1 * vj;
-                        const T u2 = fmat(pc.x0, gj0, fmat(pc.x1, gj1, pc.x2 * vj));
+                        const T u0 = -pc.b0 * vj, u1 = -pc.b1 * vj;
+                        const T u2 = fmat(pc.x0, gj0, fmat(pc.x1, gj1, -pc.c2 * vj));
                         T col[NB];
 #pragma unroll
                         for (int i = 0; i < NB; ++i) col[i] = fmat(ev.g0[i], u0, fmat(ev.g1[i], u1, ev.v[i] * u2));
 #pragma unroll
                         for (int i = 0; i < NB; ++i) col[i] = group_sum<FG>(col[i]);
                         if (wr) {
+                            const T csc = T(kNorm[j] * xsc);
 #pragma unroll
                             for (int i = 0; i < NB; ++i)
                                 if (i % FG == gq) {
-                                    const T v = T(double(col[i]) * (c_norm[i] * c_norm[j] * xsc));
+                                    const T v = col[i] * T(kNorm[i]) * csc;
                                     if (d == 0)
                                         dst[i * nbo + j] = v;
                                     else
@@ -388,7 +398,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
         for (int base = 0; base < R.QR; base += 64) {
             const int q = base + lane;
             const int tri = q < R.QR ? q / C::NQT : 0;
-            const double X0 = __shfl(ex, 0, 64), Y0 = __shfl(ey, 0, 64);
+            const double X0 = R.x0, Y0 = R.y0;
             const double X1 = __shfl(ex, tri + 1, 64), Y1 = __shfl(ey, tri + 1, 64);
             const double X2 = __shfl(ex, tri + 2, 64), Y2 = __shfl(ey, tri + 2, 64);
             if (q < R.QR) {
@@ -426,11 +436,10 @@ __device__ __forceinline__ void row_slices(const AsmArgs &A, const RowCtx &R, st
 
 // MX: neighbours may have other degrees than P (up to PN); otherwise all have degree P = PN
 template <typename T, int P, int PN, bool MX, bool ADV>
-__global__ void __launch_bounds__(256) k_row2d(AsmArgs A) {
+__global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW)) k_row2d(AsmArgs A) {
     using C = RowCfg<T, P, PN>;
     constexpr int NB = C::NB, FG = C::FG;
     const DevMesh &m = A.m;
-    const DevProblem &pr = A.pr;
     const int lane = threadIdx.x & 63;
     // the row index is uniform across the wave: keep it (and what derives from it) in scalar registers
     const int wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -504,7 +513,7 @@ __global__ void __launch_bounds__(256) k_row2d(AsmArgs A) {
     R.isq = uniform(1.0 / g.sqrt_box);
     R.hx = uniform(g.hix - g.lox);
     R.hy = uniform(g.hiy - g.loy);
-    R.tc = trig_centre(pr, 0.5 * (g.lox + g.hix), 0.5 * (g.loy + g.hiy), 0.5 * sqrt(R.hx * R.hx + R.hy * R.hy));
+    R.tc = trig_centre_of(g);
     R.tc.x0 = uniform(R.tc.x0);
     R.tc.y0 = uniform(R.tc.y0);
     R.tc.sx = uniform(R.tc.sx);
@@ -527,8 +536,23 @@ __global__ void __launch_bounds__(256) k_row2d(AsmArgs A) {
     R.dvoff = dvoff;
     R.maxdup = max(dupc, 1);
     R.gmask = gmask;
+    {
+        // lane g gets the position of the g-th set bit of gmask
+        const bool lead = (gmask >> lane) & 1ull;
+        const int gidx = __popcll(gmask & ((1ull << lane) - 1ull));
+        int tab = 0;
+        for (int k = 0; k < nv; ++k) {
+            const int gk = __shfl(gidx, k, 64);
+            const bool lk = (gmask >> k) & 1ull;
+            if (lk && gk == lane) tab = k;
+        }
+        (void)lead;
+        R.gtab = tab;
+    }
     R.ex = ex;
     R.ey = ey;
+    R.x0 = readlane_d(ex, 0);
+    R.y0 = readlane_d(ey, 0);
     R.pre_v = pre_v;
     R.pre_d = pre_d;
     row_slices<T, P, PN, MX, ADV>(A, R, std::make_integer_sequence<int, C::NSL>{});

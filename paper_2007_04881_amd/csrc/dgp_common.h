@@ -49,6 +49,7 @@ struct alignas(64) CellGeo {
     double abar;                // max of a over the volume quadrature points
     double sqrt_box;            // sqrt(|bounding box|), basis normalisation
     double area;                // |kappa|
+    double sx, cx, sy, cy;      // sin / cos (pi x), (pi y) at the box centre (0, 1, 0, 1 if unused)
 };
 
 // One loop edge of an element as the assembly needs it (32 bytes).
@@ -189,6 +190,20 @@ __device__ __forceinline__ TrigCentre trig_centre(const DevProblem &pr, double x
         sincospi(x0, &t.sx, &t.cx);
         sincospi(y0, &t.sy, &t.cy);
     }
+    return t;
+}
+
+// The same from the values stored with the element's geometry.
+__device__ __forceinline__ TrigCentre trig_centre_of(const CellGeo &g) {
+    TrigCentre t;
+    t.x0 = 0.5 * (g.lox + g.hix);
+    t.y0 = 0.5 * (g.loy + g.hiy);
+    t.sx = g.sx;
+    t.cx = g.cx;
+    t.sy = g.sy;
+    t.cy = g.cy;
+    const double hx = g.hix - g.lox, hy = g.hiy - g.loy;
+    t.near = kPi * 0.5 * sqrt(hx * hx + hy * hy) <= kNearT;
     return t;
 }
 

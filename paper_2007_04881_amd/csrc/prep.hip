@@ -247,6 +247,11 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
         g.abar = pr.a1 != 0.0 ? amax : pr.a0;
         g.sqrt_box = sqrt((hix - lox) * (hiy - loy));
         g.area = 0.5 * a2;
+        const TrigCentre t = trig_centre(pr, 0.5 * (lox + hix), 0.5 * (loy + hiy), 0.0);
+        g.sx = t.sx;
+        g.cx = t.cx;
+        g.sy = t.sy;
+        g.cy = t.cy;
         out.geo[c] = g;
     }
     if (lane == 0) {

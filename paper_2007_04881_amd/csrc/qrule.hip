@@ -14,8 +14,8 @@
 //   k_rule_init   initial rule from the network output, or the 4 x 4 Gauss
 //                 tensor rule scaled to the polygon's area
 //   k_refine      FP64 damped minimum-norm Gauss-Newton (Levenberg-Marquardt)
-//                 on the 28 moment equations, one wave per element, and the
-//                 acceptance test
+//                 on the 28 moment equations, one wave per element
+//                 (Gauss-Jordan in registers), and the acceptance test
 #include "dgp_common.h"
 #include "kernels.h"
 #include "rules_data.h"
@@ -268,41 +268,34 @@ __global__ void k_rule_init(int n, const float *__restrict__ z, const double *__
 // a step is taken only if it lowers ||Q - M||_2 (then mu /= 10), otherwise mu
 // grows tenfold and the step is recomputed.  Stops as soon as
 // max_ab |Q_ab - M_ab| / |P| <= tol (accepted) or after max_it steps
-// (rejected: the element keeps the sub-triangulation rule).  One wave per
-// element; J J^T is formed from the node tables without storing J, then
-// factored by Cholesky in LDS.
+// (rejected: the element keeps the sub-triangulation rule).
+//
+// One wave per element, each wave with its own LDS, no work-group barriers:
+// lanes k < 16 tabulate the Legendre polynomials at node k; J J^T (28 x 28,
+// lower triangle) is formed entry-parallel from the tables; lane i < 28 then holds
+// row i of J J^T + mu g I and Gauss-Jordan elimination broadcasts each pivot
+// row through scalar registers; lane c < 48 forms component c of J^T z.
 namespace {
 
+constexpr int RWAVES = 2;  // elements (waves) per work-group
+
 struct RefineLds {
-    double u[2][3 * kQrNodes];       // current and trial (nodes interleaved xi, eta; then weights)
-    double T[2][4][kQrNodes][8];     // P(xi), P'(xi), P(eta), P'(eta) at each node, degrees 0..6
-    double G0[NM][NM + 1], G[NM][NM + 1];
-    double r[2][NM], z[NM], Mm[NM];
+    double T[2][4][kQrNodes][8];  // per rule slot: P(xi), P'(xi), P(eta), P'(eta) at each node, degrees 0..6
+    double G[32][33];
+    double u[2][3 * kQrNodes];    // per rule slot: (xi_k, eta_k) interleaved, then w_k
 };
 
-// node tables and residual of rule `s` (all 64 lanes; ends with the wave in sync)
-__device__ double tables_and_residual(RefineLds &L, int s, int lane) {
-    if (lane < 2 * kQrNodes) {
-        const int k = lane & (kQrNodes - 1), eta = lane >= kQrNodes;
-        double P[7], dP[7];
-        legendre<double, 6>(L.u[s][2 * k + eta], P, dP);
-#pragma unroll
-        for (int d = 0; d < 7; ++d) {
-            L.T[s][2 * eta][k][d] = P[d];
-            L.T[s][2 * eta + 1][k][d] = dP[d];
-        }
-    }
-    __syncthreads();
-    double rm = 0.0;
-    if (lane < NM) {
-        const int a = c_ma[lane], b = c_mb[lane];
-        double Q = 0.0;
-        for (int k = 0; k < kQrNodes; ++k) Q += L.u[s][2 * kQrNodes + k] * L.T[s][0][k][a] * L.T[s][2][k][b];
-        rm = Q - L.Mm[lane];
-        L.r[s][lane] = rm;
-    }
-    __syncthreads();
-    return rm;
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -314,15 +307,66 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// exponents of moment m (total degree order, a descending)
+__host__ __device__ constexpr int mom_a(int m) {
+    int d = 0;
+    while ((d + 1) * (d + 2) / 2 <= m) ++d;
+    return d - (m - d * (d + 1) / 2);
+}
+__host__ __device__ constexpr int mom_b(int m) {
+    int d = 0;
+    while ((d + 1) * (d + 2) / 2 <= m) ++d;
+    return m - d * (d + 1) / 2;
+}
+
+// tables of rule slot s (lanes < 32), then the residual of moment lane m < 28 (0 on other lanes)
+__device__ double tables_residual(RefineLds &L, int s, int lane, int am, int bm, double Mm) {
+    if (lane < 2 * kQrNodes) {
+        const int k = lane & (kQrNodes - 1), eta = lane >= kQrNodes;
+        double P[7], dP[7];
+        legendre<double, 6>(L.u[s][2 * k + eta], P, dP);
+#pragma unroll
+        for (int d = 0; d < 7; ++d) {
+            L.T[s][2 * eta][k][d] = P[d];
+            L.T[s][2 * eta + 1][k][d] = dP[d];
+        }
+    }
+    wave_sync();
+    double r = 0.0;
+    if (lane < NM) {
+        double Q = 0.0;
+        for (int k = 0; k < kQrNodes; ++k) Q += L.u[s][2 * kQrNodes + k] * L.T[s][0][k][am] * L.T[s][2][k][bm];
+        r = Q - Mm;
+    }
+    return r;
+}
+
+// entry (m, c) of J at rule slot s (m < 28 real rows; rows 28..31 are zero)
+__device__ __forceinline__ double jac(const RefineLds &L, int s, int m, int c) {
+    if (m >= NM) return 0.0;
+    const int a = mom_a(m), b = mom_b(m);
+    if (c >= 2 * kQrNodes) {
+        const int k = c - 2 * kQrNodes;
+        return L.T[s][0][k][a] * L.T[s][2][k][b];
+    }
+    const int k = c >> 1;
+    const double w = L.u[s][2 * kQrNodes + k];
+    return (c & 1) ? w * L.T[s][0][k][a] * L.T[s][3][k][b] : w * L.T[s][1][k][a] * L.T[s][2][k][b];
+}
+
 }  // namespace
 
-__global__ void __launch_bounds__(64) k_refine(int n, const double *__restrict__ mom, const double *__restrict__ parea,
-                                               const uint8_t *__restrict__ eligible, double *nodes, double *weights,
-                                               uint8_t *accepted, double *residual, int32_t *iters, int max_it,
-                                               double tol, double mu0) {
-    __shared__ RefineLds L;
-    const int c = blockIdx.x;
-    const int lane = threadIdx.x;
+__global__ void __launch_bounds__(64 * RWAVES) k_refine(int n, const double *__restrict__ mom,
+                                                        const double *__restrict__ parea,
+                                                        const uint8_t *__restrict__ eligible, double *nodes,
+                                                        double *weights, uint8_t *accepted, double *residual,
+                                                        int32_t *iters, int max_it, double tol, double mu0) {
+    __shared__ RefineLds Lw[RWAVES];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = blockIdx.x * RWAVES + wv;
+    if (c >= n) return;
+    RefineLds &L = Lw[wv];
     if (!eligible[c]) {
         if (lane == 0) {
             accepted[c] = 0;
@@ -334,12 +378,13 @@ __global__ void __launch_bounds__(64) k_refine(int n, const double *__restrict__
     const double A = parea[c];
     if (lane < 2 * kQrNodes) L.u[0][lane] = nodes[(int64_t)c * 2 * kQrNodes + lane];
     if (lane < kQrNodes) L.u[0][2 * kQrNodes + lane] = weights[(int64_t)c * kQrNodes + lane];
-    if (lane < NM) L.Mm[lane] = mom[(int64_t)c * NM + lane];
-    __syncthreads();
+    const int am = lane < NM ? mom_a(lane) : 0, bm = lane < NM ? mom_b(lane) : 0;
+    const double Mm = lane < NM ? mom[(int64_t)c * NM + lane] : 0.0;
+    wave_sync();
     int cur = 0, it = 0;
     bool ok = false;
     double mu = mu0;
-    double rm = tables_and_residual(L, cur, lane);
+    double rm = tables_residual(L, cur, lane, am, bm, Mm);
     double rn2 = wave_sum(rm * rm);
     double res = wave_max(fabs(rm)) / A;
     for (;;) {
@@ -348,95 +393,70 @@ __global__ void __launch_bounds__(64) k_refine(int n, const double *__restrict__
             break;
         }
         if (it >= max_it || !(res < 1e300)) break;
-        // G0 = J J^T (lower triangle) at the current rule
+        // G0 = J J^T: lanes over the 406 entries of the lower triangle (mirrored)
         for (int idx = lane; idx < NM * (NM + 1) / 2; idx += 64) {
             int m_ = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
             if ((m_ + 1) * (m_ + 2) / 2 <= idx) ++m_;
             if (m_ * (m_ + 1) / 2 > idx) --m_;
             const int n_ = idx - m_ * (m_ + 1) / 2;
-            const int am = c_ma[m_], bm = c_mb[m_], an = c_ma[n_], bn = c_mb[n_];
-            double g = 0.0;
+            const int a1 = mom_a(m_), b1 = mom_b(m_), a2 = mom_a(n_), b2 = mom_b(n_);
+            const double(*T)[kQrNodes][8] = L.T[cur];
+            double gv = 0.0;
             for (int k = 0; k < kQrNodes; ++k) {
                 const double wk = L.u[cur][2 * kQrNodes + k];
-                const double(*T)[kQrNodes][8] = L.T[cur];
-                const double vm = T[0][k][am] * T[2][k][bm], vn = T[0][k][an] * T[2][k][bn];
-                const double xm = T[1][k][am] * T[2][k][bm], xn = T[1][k][an] * T[2][k][bn];
-                const double ym = T[0][k][am] * T[3][k][bm], yn = T[0][k][an] * T[3][k][bn];
-                g += wk * wk * (xm * xn + ym * yn) + vm * vn;
+                const double vm = T[0][k][a1] * T[2][k][b1], vn = T[0][k][a2] * T[2][k][b2];
+                const double xm = T[1][k][a1] * T[2][k][b1], xn = T[1][k][a2] * T[2][k][b2];
+                const double ym = T[0][k][a1] * T[3][k][b1], yn = T[0][k][a2] * T[3][k][b2];
+                gv += wk * wk * (xm * xn + ym * yn) + vm * vn;
             }
-            L.G0[m_][n_] = g;
+            L.G[m_][n_] = gv;
+            L.G[n_][m_] = gv;
         }
-        __syncthreads();
-        const double gmax = wave_max(lane < NM ? L.G0[lane][lane] : 0.0);
+        wave_sync();
+        double grow[NM];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) grow[k] = lane < NM ? L.G[lane][k] : 0.0;
+        const double gmax = wave_max(lane < NM ? L.G[lane][lane] : 0.0);
         bool taken = false;
         while (mu <= 1e6) {
             const double lam = mu * gmax;
-            for (int idx = lane; idx < NM * (NM + 1); idx += 64) {
-                const int i = idx / (NM + 1), j = idx - i * (NM + 1);
-                if (j <= i) L.G[i][j] = L.G0[i][j] + (i == j ? lam : 0.0);
-            }
-            if (lane < NM) L.z[lane] = L.r[cur][lane];
-            __syncthreads();
-            // Cholesky, right-looking
+            // Gauss-Jordan on (G0 + lam I) z = r, lane i owns row i
+            double g[NM];
+#pragma unroll
+            for (int k = 0; k < NM; ++k) g[k] = grow[k] + (k == lane ? lam : 0.0);
+            double z = rm, diag = 1.0;
             bool spd = true;
+#pragma unroll
             for (int j = 0; j < NM; ++j) {
-                const double d = L.G[j][j];
-                if (!(d > 0.0)) {
-                    spd = false;
-                    break;
-                }
-                const double piv = sqrt(d);
-                __syncthreads();
-                if (lane == 0) L.G[j][j] = piv;
-                if (lane > j && lane < NM) L.G[lane][j] /= piv;
-                __syncthreads();
-                if (lane > j && lane < NM) {
-                    const double lij = L.G[lane][j];
-                    for (int k = j + 1; k <= lane; ++k) L.G[lane][k] -= lij * L.G[k][j];
-                }
-                __syncthreads();
+                const double piv = readlane_d(g[j], j);
+                if (!(piv > 0.0)) spd = false;
+                const double inv = 1.0 / piv;
+                const double zj = readlane_d(z, j);
+                const double f = (lane == j || lane >= NM) ? 0.0 : g[j] * inv;
+#pragma unroll
+                for (int k = j + 1; k < NM; ++k) g[k] -= f * readlane_d(g[k], j);
+                z -= f * zj;
+                if (lane == j) diag = piv;
             }
             if (!spd) {
-                __syncthreads();
                 mu *= 10.0;
                 continue;
             }
-            // L y = r, then L^T z = y
-            for (int j = 0; j < NM; ++j) {
-                const double yj = L.z[j] / L.G[j][j];
-                __syncthreads();
-                if (lane == j) L.z[j] = yj;
-                if (lane > j && lane < NM) L.z[lane] -= L.G[lane][j] * yj;
-                __syncthreads();
-            }
-            for (int j = NM - 1; j >= 0; --j) {
-                const double zj = L.z[j] / L.G[j][j];
-                __syncthreads();
-                if (lane == j) L.z[j] = zj;
-                if (lane < j) L.z[lane] -= L.G[j][lane] * zj;
-                __syncthreads();
-            }
-            // trial rule u - J^T z
+            z = lane < NM ? z / diag : 0.0;
+            // trial rule u - J^T z (lane c < 48 owns component c)
             const int nx = 1 - cur;
-            if (lane < 2 * kQrNodes) {
-                const int k = lane >> 1, eta = lane & 1;
+            if (lane < 3 * kQrNodes) {
                 double du = 0.0;
-                for (int m_ = 0; m_ < NM; ++m_) {
-                    const int a = c_ma[m_], b = c_mb[m_];
-                    du += L.z[m_] * (eta ? L.T[cur][0][k][a] * L.T[cur][3][k][b] : L.T[cur][1][k][a] * L.T[cur][2][k][b]);
-                }
-                L.u[nx][lane] = L.u[cur][lane] - du * L.u[cur][2 * kQrNodes + k];
-            } else if (lane < 3 * kQrNodes) {
-                const int k = lane - 2 * kQrNodes;
-                double du = 0.0;
-                for (int m_ = 0; m_ < NM; ++m_) du += L.z[m_] * L.T[cur][0][k][c_ma[m_]] * L.T[cur][2][k][c_mb[m_]];
+#pragma unroll
+                for (int m_ = 0; m_ < NM; ++m_) du += jac(L, cur, m_, lane) * readlane_d(z, m_);
                 L.u[nx][lane] = L.u[cur][lane] - du;
             }
-            __syncthreads();
-            const double rt = tables_and_residual(L, nx, lane);
+            wave_sync();
+            const double rt = tables_residual(L, nx, lane, am, bm, Mm);
             const double rtn2 = wave_sum(rt * rt);
             if (rtn2 < rn2) {
                 cur = nx;
+                rm = rt;
                 rn2 = rtn2;
                 res = wave_max(fabs(rt)) / A;
                 mu = fmax(mu * 0.1, 1e-15);
@@ -448,7 +468,7 @@ __global__ void __launch_bounds__(64) k_refine(int n, const double *__restrict__
         if (!taken) break;
         ++it;
     }
-    __syncthreads();
+    wave_sync();
     if (lane < 2 * kQrNodes) nodes[(int64_t)c * 2 * kQrNodes + lane] = L.u[cur][lane];
     if (lane < kQrNodes) weights[(int64_t)c * kQrNodes + lane] = L.u[cur][2 * kQrNodes + lane];
     if (lane == 0) {
@@ -479,8 +499,8 @@ void launch_refine(int n, const double *mom, const double *parea, const uint8_t 
                    double *weights, uint8_t *accepted, double *residual, int32_t *iters, int max_it, double tol,
                    double mu0, hipStream_t st) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_refine, dim3(n), dim3(64), 0, st, n, mom, parea, eligible, nodes, weights, accepted, residual,
-                       iters, max_it, tol, mu0);
+    hipLaunchKernelGGL(k_refine, dim3((n + RWAVES - 1) / RWAVES), dim3(64 * RWAVES), 0, st, n, mom, parea, eligible,
+                       nodes, weights, accepted, residual, iters, max_it, tol, mu0);
 }
 
 }  // namespace dgp
