@@ -138,13 +138,8 @@ def reduced_rule_study(D, torch, steps, warmup, train_polygons, train_epochs):
     for mode, name in ((D.RULE_PLAIN, "plain"), (D.RULE_REDUCED, "reduced")):
         ctx.graph_capture(1, params, D.F32, vals, rhs, rule_mode=mode)
         t[name] = _replay_ms(ctx, D, torch, steps, warmup)
-        ctx.set_timing(True)
-        ks = []
-        for _ in range(10):
-            ctx.assemble(params, D.F32, vals, rhs, rule_mode=mode)
-            ks.append(ctx.kernel_ms("assemble"))
-        ctx.set_timing(False)
-        kern[name] = sorted(ks)[len(ks) // 2]
+        ctx.assemble(params, D.F32, vals, rhs, rule_mode=mode)
+        kern[name] = ctx.time_kernels(10)[1]
     gain = kern["plain"] - kern["reduced"]
     rulegen = net["features_ms"] + net["network_ms"] + net["refine_ms"]
     ctx.close()
@@ -217,15 +212,11 @@ def main():
     torch.cuda.synchronize()
     ms_values = (time.perf_counter() - t0) * 1e3 / args.steps
 
-    # per-kernel device time from HIP events on the context stream
-    ctx.set_timing(True)
-    kms = {"prep": [], "assemble": []}
-    for _ in range(max(20, args.warmup)):
-        ctx.run(params, D.F32, vals, rhs)
-        for k in kms:
-            kms[k].append(ctx.kernel_ms(k))
-    ctx.set_timing(False)
-    avg = {k: sum(v[5:]) / len(v[5:]) for k, v in kms.items()}
+    # per-launch device time of the kernels: HIP events on the context stream
+    # around 50 back-to-back re-launches of the last step's kernels
+    ctx.run(params, D.F32, vals, rhs)
+    prep_ms, asm_ms = ctx.time_kernels(50)
+    avg = {"prep": prep_ms, "assemble": asm_ms}
     abytes = algorithmic_bytes(mesh, info, 4)
     achieved = abytes / (avg["assemble"] * 1e-3) / 1e9
 

@@ -159,6 +159,13 @@ dgp_status dgp_graph_launch(dgp_ctx *ctx);
 dgp_status dgp_set_timing(dgp_ctx *ctx, int enable);
 dgp_status dgp_kernel_ms(dgp_ctx *ctx, const char *name, float *ms);
 
+/* Device time per launch of the preparation kernels and of the assembly
+ * kernel(s) of the last dgp_run / dgp_assemble, from `reps` back-to-back
+ * re-launches with the same arguments between two HIP events on the context
+ * stream (values rewritten, pattern untouched; that call's output buffers
+ * must still be allocated).  Synchronous. */
+dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assemble_ms);
+
 /* ---------------------------------------------------------------------
  * Reduced volume rules for polygons (an extension of Section 3: the paper
  * integrates on the fan sub-triangles only).  Every element with at most 12

@@ -68,7 +68,7 @@ class TrainStats(C.Structure):
 
 EXPORTS = ["dgp_create", "dgp_destroy", "dgp_set_stream", "dgp_last_error", "dgp_mesh_upload", "dgp_pattern",
            "dgp_pattern_copy", "dgp_assemble", "dgp_run", "dgp_graph_capture", "dgp_graph_launch",
-           "dgp_set_timing", "dgp_kernel_ms", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
+           "dgp_set_timing", "dgp_kernel_ms", "dgp_time_kernels", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
            "dgp_qrule_cell_data", "dgp_train_polygons", "dgp_mlp_forward", "dgp_mlp_loss_grad", "dgp_adam_step",
            "dgp_mlp_train"]
 
@@ -112,6 +112,7 @@ def lib():
                                     C.POINTER(TrainStats)]
         L.dgp_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.dgp_kernel_ms.argtypes = [C.c_void_p, C.c_char_p, C.POINTER(C.c_float)]
+        L.dgp_time_kernels.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         _lib = L
     return _lib
 
@@ -245,6 +246,12 @@ class Context:
 
     def set_timing(self, on: bool):
         self._check(lib().dgp_set_timing(self._h, 1 if on else 0), "dgp_set_timing")
+
+    def time_kernels(self, reps=50):
+        """(prep, assembly) device ms per launch, averaged over reps back-to-back re-launches."""
+        a, b = C.c_float(), C.c_float()
+        self._check(lib().dgp_time_kernels(self._h, reps, C.byref(a), C.byref(b)), "dgp_time_kernels")
+        return a.value, b.value
 
     def kernel_ms(self, name: str) -> float:
         ms = C.c_float()

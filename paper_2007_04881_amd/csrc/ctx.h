@@ -56,6 +56,12 @@ struct dgp_ctx {
     uint8_t *qr_elig = nullptr;    // [n_cells]
     uint8_t *qr_ok = nullptr;      // [n_cells]
 
+    // the last step's arguments (re-launched by dgp_time_kernels)
+    bool has_last = false;
+    dgp::DevProblem last_pr{};
+    int last_precision = 0, last_rule = 0;
+    void *last_vals = nullptr, *last_rhs = nullptr;
+
     bool timing = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool ev_pattern = false, ev_assemble = false;

@@ -51,6 +51,7 @@ static void free_mesh(dgp_ctx *c) {
     c->work = nullptr;
     dgp_free_qrule(c);
     c->has_mesh = false;
+    c->has_last = false;
     free_pattern(c);
     free_graph(c);
 }
@@ -320,12 +321,8 @@ static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int
     return DGP_OK;
 }
 
-// One step: preparation kernel, then the assembly kernel (values = 0: pattern only).
-static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
-                               int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed) {
-    if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
-    launch_prep(ctx->dm, dp, ctx->prep, st);
-    if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
+static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
+                                  int write_pattern, void *vals, void *rhs, hipStream_t st) {
     AsmArgs a;
     a.m = ctx->dm;
     a.pr = dp;
@@ -361,10 +358,29 @@ static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision
                 return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
         }
     }
+    return DGP_OK;
+}
+
+// One step: preparation kernels, then the assembly kernel(s) (values = 0: pattern only).
+static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
+                               int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed) {
+    if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
+    launch_prep(ctx->dm, dp, ctx->prep, st);
+    if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
+    dgp_status s = launch_assembly(ctx, dp, precision, rule_mode, values, write_pattern, vals, rhs, st);
+    if (s) return s;
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[2], st));
     HIPCHK(ctx, hipGetLastError());
     ctx->ev_pattern = timed;
     ctx->ev_assemble = timed;
+    if (values) {
+        ctx->has_last = true;
+        ctx->last_pr = dp;
+        ctx->last_precision = precision;
+        ctx->last_rule = rule_mode;
+        ctx->last_vals = vals;
+        ctx->last_rhs = rhs;
+    }
     return DGP_OK;
 }
 
@@ -424,6 +440,31 @@ dgp_status dgp_graph_launch(dgp_ctx *ctx) {
 dgp_status dgp_set_timing(dgp_ctx *ctx, int enable) {
     if (!ctx) return DGP_EINVAL;
     ctx->timing = enable != 0;
+    return DGP_OK;
+}
+
+dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assemble_ms) {
+    if (!ctx || reps < 1) return DGP_EINVAL;
+    if (!ctx->has_last) return fail(ctx, DGP_ESTATE, "dgp_time_kernels before an assembly");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
+    for (int i = 0; i < reps; ++i) launch_prep(ctx->dm, ctx->last_pr, ctx->prep, st);
+    HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
+    for (int i = 0; i < reps; ++i) {
+        dgp_status s = launch_assembly(ctx, ctx->last_pr, ctx->last_precision, ctx->last_rule, 1, 0, ctx->last_vals,
+                                       ctx->last_rhs, st);
+        if (s) return s;
+    }
+    HIPCHK(ctx, hipEventRecord(ctx->ev[2], st));
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipEventSynchronize(ctx->ev[2]));
+    float a = 0.0f, b = 0.0f;
+    HIPCHK(ctx, hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+    HIPCHK(ctx, hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+    if (prep_ms) *prep_ms = a / reps;
+    if (assemble_ms) *assemble_ms = b / reps;
+    ctx->ev_pattern = ctx->ev_assemble = false;
     return DGP_OK;
 }
 

@@ -126,6 +126,11 @@ def test_deterministic_and_graph_replay():
     ctx.assemble(params, D.F32, v2, r2)
     torch.cuda.synchronize()
     assert torch.equal(v1, v2) and torch.equal(r1, r2)
+    # re-launching the step's kernels for timing rewrites the same values
+    prep_ms, asm_ms = ctx.time_kernels(3)
+    torch.cuda.synchronize()
+    assert prep_ms > 0.0 and asm_ms > 0.0
+    assert torch.equal(v1, v2) and torch.equal(r1, r2)
     for what in (0, 1):
         v3, r3 = ctx.outputs(D.F32)
         ctx.graph_capture(what, params, D.F32, v3, r3)
