@@ -96,3 +96,83 @@ def polygon_integral(xy, c):
             if c[a, b] != 0.0:
                 s += c[a, b] * polygon_monomial(xy, a, b)
     return s
+
+
+# ----------------------------------------------------------------- 3D
+def basis_polys_3d(p, lo, hi):
+    """Basis functions as coefficient arrays C[a, b, c] of xi^a eta^b zeta^c in
+    the box coordinates."""
+    box = np.prod(np.asarray(hi)[:3] - np.asarray(lo)[:3])
+    out = []
+    for a, b, c in basis_exponents(3, p):
+        s = np.sqrt((2 * a + 1) * (2 * b + 1) * (2 * c + 1) / box)
+        pa, pb, pc = (L.leg2poly([0] * k + [1]) for k in (a, b, c))
+        out.append(s * pa[:, None, None] * pb[None, :, None] * pc[None, None, :])
+    return out
+
+
+def d3(c, axis):
+    """Derivative along a box axis of a 3D coefficient array."""
+    if c.shape[axis] == 1:
+        return np.zeros_like(c)
+    return P.polyder(c, axis=axis)
+
+
+def mul3(a, b):
+    out = np.zeros(tuple(a.shape[k] + b.shape[k] - 1 for k in range(3)))
+    for idx in np.ndindex(*a.shape):
+        if a[idx] != 0.0:
+            i, j, k = idx
+            out[i:i + b.shape[0], j:j + b.shape[1], k:k + b.shape[2]] += a[idx] * b
+    return out
+
+
+def triangle_rule_collapsed(n):
+    """n^2-point rule on the unit triangle from a Gauss product on the square
+    collapsed onto it (Duffy map); exact for total degree 2n - 2.  Returns
+    barycentric points [n^2, 3] and weights summing to 1."""
+    t, w = np.polynomial.legendre.leggauss(n)
+    u, wu = 0.5 * (t + 1), 0.5 * w
+    pts, wts = [], []
+    for i in range(n):
+        for j in range(n):
+            s = u[i]
+            r = (1 - s) * u[j]
+            pts.append((1 - s - r, s, r))
+            wts.append(wu[i] * wu[j] * (1 - s))
+    wts = np.array(wts)
+    return np.array(pts), wts / wts.sum()
+
+
+def cell_triangles_outward(m, c):
+    """The boundary triangles of polyhedral cell c as [k, 3, 3] vertex
+    coordinates, each ordered so that its normal points out of the cell."""
+    xyz = np.stack([m.x, m.y, m.z], 1)
+    out = []
+    for f in m.cell_face[m.cell_face_ptr[c]:m.cell_face_ptr[c + 1]]:
+        v = xyz[m.face_vtx[3 * f:3 * f + 3]]
+        o = xyz[m.face_opp[f]]
+        nrm = np.cross(v[1] - v[0], v[2] - v[0])
+        away_from_opp = np.dot(nrm, o - v[0]) < 0
+        left = m.face_cell[2 * f] == c
+        if away_from_opp != left:
+            v = v[[0, 2, 1]]
+        out.append(v)
+    return np.array(out)
+
+
+def polyhedron_integral_box(tris_xi, c, n_rule=6):
+    """int over the polyhedron (triangles given in box coordinates, outward) of
+    the polynomial c[a, b, c] in (xi, eta, zeta), by the divergence theorem with
+    the xi-antiderivative, in box coordinates (multiply by the box Jacobian)."""
+    G = P.polyint(c, axis=0)
+    bary, w = triangle_rule_collapsed(n_rule)
+    s = 0.0
+    for v in tris_xi:
+        S1 = 0.5 * np.cross(v[1] - v[0], v[2] - v[0])[0]
+        if S1 == 0.0:
+            continue
+        x = bary @ v
+        vals = P.polyval3d(x[:, 0], x[:, 1], x[:, 2], G)
+        s += S1 * np.dot(w, vals)
+    return s
