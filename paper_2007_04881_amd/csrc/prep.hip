@@ -67,15 +67,15 @@ __device__ __forceinline__ double gmin_d(double v) {
 }
 
 template <int DEG>
-__device__ double max_a_on_triangle(const DevProblem &pr, double x0, double y0, double x1, double y1, double x2,
-                                    double y2) {
+__device__ double max_a_on_triangle(const DevProblem &pr, const TrigCentre &tc, double x0, double y0, double x1,
+                                    double y1, double x2, double y2) {
     const double *L = DEG == 4 ? c_tri4_l : DEG == 6 ? c_tri6_l : c_tri8_l;
     const int n = DEG == 4 ? DGP_TRI4_N : DEG == 6 ? DGP_TRI6_N : DGP_TRI8_N;
     double amax = -1e300;
     for (int q = 0; q < n; ++q) {
         double px = L[3 * q] * x0 + L[3 * q + 1] * x1 + L[3 * q + 2] * x2;
         double py = L[3 * q] * y0 + L[3 * q + 1] * y1 + L[3 * q + 2] * y2;
-        amax = fmax(amax, coef_a(pr, px, py));
+        amax = fmax(amax, coef_a_near(pr, tc, px, py));
     }
     return amax;
 }
@@ -87,6 +87,7 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
 
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
+    const int base = threadIdx.x & ~(G - 1);  // first lane of this element's group
     const int tile = blockIdx.x;
     const int c = tile * CPB + grp;
     const bool valid = c < m.n_cells;
@@ -144,24 +145,26 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
             }
         }
     }
-    if (valid && pr.a1 != 0.0) {
-        const int v0 = m.cell_vtx[s];
-        const double x0 = m.x[v0], y0 = m.y[v0];
-        for (int t = lane; t + 2 < nv; t += G) {
-            const int v1 = m.cell_vtx[s + t + 1], v2 = m.cell_vtx[s + t + 2];
-            const double x1 = m.x[v1], y1 = m.y[v1], x2 = m.x[v2], y2 = m.y[v2];
-            double am = p <= 2 ? max_a_on_triangle<4>(pr, x0, y0, x1, y1, x2, y2)
-                      : p == 3 ? max_a_on_triangle<6>(pr, x0, y0, x1, y1, x2, y2)
-                               : max_a_on_triangle<8>(pr, x0, y0, x1, y1, x2, y2);
-            amax = fmax(amax, am);
-        }
-    }
     lox = gmin_d(lox);
     loy = gmin_d(loy);
     hix = gmax_d(hix);
     hiy = gmax_d(hiy);
     a2 = gsum_d(a2);
     d2 = gmax_d(d2);
+    // sin/cos at the box centre, then abar over the volume points by angle addition from it
+    const double hxb = hix - lox, hyb = hiy - loy;
+    const TrigCentre tcen = trig_centre(pr, 0.5 * (lox + hix), 0.5 * (loy + hiy), 0.5 * sqrt(hxb * hxb + hyb * hyb));
+    const double ax0 = __shfl(xq[0], base, 64), ay0 = __shfl(yq[0], base, 64);  // vertex 0 sits in the group's first lane
+    if (valid && pr.a1 != 0.0) {
+        for (int t = lane; t + 2 < nv; t += G) {
+            const int v1 = m.cell_vtx[s + t + 1], v2 = m.cell_vtx[s + t + 2];
+            const double x1 = m.x[v1], y1 = m.y[v1], x2 = m.x[v2], y2 = m.y[v2];
+            double am = p <= 2 ? max_a_on_triangle<4>(pr, tcen, ax0, ay0, x1, y1, x2, y2)
+                      : p == 3 ? max_a_on_triangle<6>(pr, tcen, ax0, ay0, x1, y1, x2, y2)
+                               : max_a_on_triangle<8>(pr, tcen, ax0, ay0, x1, y1, x2, y2);
+            amax = fmax(amax, am);
+        }
+    }
     amax = gmax_d(amax);
 
     // ------------------------------------------------------ row size
@@ -169,7 +172,6 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     bool first[SLOTS];
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) first[q] = nb[q] >= 0;
-    const int base = threadIdx.x & ~(G - 1);
 #pragma unroll
     for (int q2 = 0; q2 < SLOTS; ++q2) {
         for (int l2 = 0; l2 < G; ++l2) {
@@ -247,11 +249,10 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
         g.abar = pr.a1 != 0.0 ? amax : pr.a0;
         g.sqrt_box = sqrt((hix - lox) * (hiy - loy));
         g.area = 0.5 * a2;
-        const TrigCentre t = trig_centre(pr, 0.5 * (lox + hix), 0.5 * (loy + hiy), 0.0);
-        g.sx = t.sx;
-        g.cx = t.cx;
-        g.sy = t.sy;
-        g.cy = t.cy;
+        g.sx = tcen.sx;
+        g.cx = tcen.cx;
+        g.sy = tcen.sy;
+        g.cy = tcen.cy;
         out.geo[c] = g;
     }
     if (lane == 0) {
