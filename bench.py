@@ -154,6 +154,35 @@ def reduced_rule_study(D, torch, steps, warmup, train_polygons, train_epochs):
             "break_even_assemblies": (rulegen / gain) if gain > 0 else None}
 
 
+def polyhedra_study(D, torch, steps, warmup):
+    """3D Poisson (A = I) on the 128^3-cube Kuhn mesh agglomerated into 32,768
+    polyhedra (about 384 tetrahedra each), p = 2 (10 dofs per cell): the whole
+    path replayed from a graph, and the per-launch kernel times, FP32 and FP64."""
+    from meshgen import config_mesh, problem_params
+    log("polyhedra: 128^3 Kuhn cubes, 32,768 cells")
+    t0 = time.perf_counter()
+    mesh = config_mesh(4)
+    gen_s = time.perf_counter() - t0
+    params = problem_params(4)
+    ctx = D.Context(0)
+    ctx.upload(mesh)
+    info = ctx.pattern()
+    out = {"workload": "3D Poisson, 128^3 Kuhn tetrahedra agglomerated into 32768 polyhedra, p=2",
+           "cells": mesh.n_cells, "tetrahedra": int(mesh.cell_ptr[-1] // 4), "faces": mesh.n_faces,
+           "nnzb": info.nnzb, "n_vals": info.n_vals, "n_dofs": info.n_dofs, "mesh_generation_s": gen_s}
+    for prec, name in ((D.F32, "f32"), (D.F64, "f64")):
+        vals, rhs = ctx.outputs(prec)
+        ctx.graph_capture(0, params, prec, vals, rhs)
+        ms = _replay_ms(ctx, D, torch, steps, warmup)
+        ctx.run(params, prec, vals, rhs)
+        prep_ms, asm_ms = ctx.time_kernels(10)
+        out[name] = {"ms_per_step": ms, "block_nnz_per_s": info.nnzb / (ms * 1e-3),
+                     "kernel_ms": {"prep": prep_ms, "assemble": asm_ms}}
+        del vals, rhs
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +190,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-rule study")
+    ap.add_argument("--no-3d", action="store_true", help="skip the polyhedral (3D) workload")
     ap.add_argument("--train-polygons", type=int, default=1_000_000)
     ap.add_argument("--train-epochs", type=int, default=30)
     args = ap.parse_args()
@@ -247,6 +277,8 @@ def main():
     ctx.close()
     if not args.no_reduced:
         out["reduced_rules"] = reduced_rule_study(D, torch, 20, 3, args.train_polygons, args.train_epochs)
+    if not args.no_3d:
+        out["polyhedra"] = polyhedra_study(D, torch, 20, 3)
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mesh, params)

@@ -60,31 +60,46 @@ typedef int32_t dgp_status;
 
 #define DGP_MLP_PARAMS 43952 /* FP32 parameters of the rule network */
 
-#define DGP_U_SIN 0  /* manufactured u = sin(pi x) sin(pi y) */
+#define DGP_U_SIN 0  /* manufactured u = sin(pi x) sin(pi y) (times sin(pi z) in 3D) */
 #define DGP_U_POLY 1 /* u = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 y^2 + c6 z^2 + c7 xy + c8 xz + c9 yz */
 
 typedef struct dgp_ctx dgp_ctx;
 
 /* Polytopic mesh, host memory; dgp_mesh_upload copies every array (the
- * caller keeps ownership).  2D only in this version (dim = 2). */
+ * caller keeps ownership).
+ *
+ * dim = 2: polygons.  cell_vtx holds each cell's counter-clockwise vertex loop
+ *   (the first vertex is the apex of the fan of sub-triangles, Section 3);
+ *   face k of a cell is the edge (v_k, v_{k+1}) of its loop, cell_face_ptr
+ *   equals cell_ptr; face_vtx holds 2 ids per edge, lower id first; degrees
+ *   1..4; at most 24 edges per cell.
+ * dim = 3: polyhedra, each the union of the tetrahedra whose 4 vertex ids it
+ *   lists in cell_vtx (cell_ptr in multiples of 4).  Its faces are the
+ *   triangles of that union's boundary (3 ids each in face_vtx), listed in
+ *   cell_face / cell_face_ptr in any order; face_opp names the vertex of the
+ *   left cell's tetrahedron opposite the triangle (it fixes the outward
+ *   normal); degrees 1..2 (the degree-4 tetrahedron and triangle rules);
+ *   at most 1024 faces per cell.  dgp_pattern fails with DGP_EUNSUPPORTED if
+ *   a cell's boundary has more than 768 distinct vertices. */
 typedef struct {
-    int32_t dim;
+    int32_t dim;                  /* 2 or 3 */
     int64_t n_vertices;
     const double *x, *y, *z;      /* [n_vertices]; z may be NULL in 2D */
     int64_t n_cells;
-    const int64_t *cell_ptr;      /* [n_cells+1] */
-    const int32_t *cell_vtx;      /* counter-clockwise vertex loop; first vertex = fan apex */
-    const int8_t *cell_p;         /* [n_cells] degree, 1..4 */
-    const int64_t *cell_face_ptr; /* [n_cells+1]; 2D: equal to cell_ptr */
-    const int32_t *cell_face;     /* face k of a cell is the edge (v_k, v_{k+1}) of its loop */
+    const int64_t *cell_ptr;      /* [n_cells+1] offsets into cell_vtx */
+    const int32_t *cell_vtx;      /* 2D: vertex loop; 3D: 4 ids per tetrahedron */
+    const int8_t *cell_p;         /* [n_cells] degree */
+    const int64_t *cell_face_ptr; /* [n_cells+1] offsets into cell_face */
+    const int32_t *cell_face;     /* faces of each cell */
     int64_t n_faces;
-    const int32_t *face_vtx;      /* [2 n_faces] edge vertices, lower id first (canonical order) */
+    const int32_t *face_vtx;      /* [dim n_faces] face vertex ids, in the order the face rule uses */
     const int32_t *face_cell;     /* [2 n_faces] left, right cell; right = -1 on the boundary */
     const int8_t *face_bc;        /* [n_faces] 0 interior, 1 Dirichlet, 2 Neumann */
-    const int32_t *face_opp;      /* 3D only; may be NULL */
+    const int32_t *face_opp;      /* [n_faces] 3D only (may be NULL in 2D) */
 } dgp_mesh_desc;
 
-/* -div(a grad u) + b . grad u + c u = f, a(x) = a0 + a1 sin(2 pi x) cos(2 pi y);
+/* -div(a grad u) + b . grad u + c u = f, a(x) = a0 + a1 sin(2 pi x) cos(2 pi y)
+ * (3D meshes: a1 must be 0, DGP_EUNSUPPORTED otherwise), b and c constant;
  * f, Dirichlet data g_D = u and Neumann data g_N = n . (a grad u) come from the
  * manufactured u and are evaluated on the device at quadrature points. */
 typedef struct {

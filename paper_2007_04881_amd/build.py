@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgpoly.so")
-SOURCES = ["runtime.hip", "learned_rt.hip", "prep.hip", "assemble_row.hip", "qrule.hip", "mlp.hip"]
+SOURCES = ["runtime.hip", "learned_rt.hip", "prep.hip", "assemble_row.hip", "prep3d.hip", "assemble3d.hip",
+           "qrule.hip", "mlp.hip"]
 ARCH = os.environ.get("DGP_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled: the compiler must not emit

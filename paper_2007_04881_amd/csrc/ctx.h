@@ -9,6 +9,7 @@
 
 #include "../../include/dgpoly.h"
 #include "dgp_common.h"
+#include "dgp3d.h"
 
 struct dgp_ctx {
     int device = 0;
@@ -35,6 +36,8 @@ struct dgp_ctx {
     // preparation outputs and the assembly's bookkeeping (one allocation)
     void *work = nullptr;
     dgp::PrepOut prep{};
+    dgp::Prep3Out prep3{};  // 3D meshes
+    int64_t n_cell_face = 0;
     int n_tiles = 0;
 
 

@@ -30,7 +30,7 @@ struct DevMesh {
     int32_t n_cells;
     int32_t n_faces;
     int32_t n_vertices;
-    const double *x, *y;
+    const double *x, *y, *z;  // z: 3D only
     const int64_t *cell_ptr;
     const int32_t *cell_vtx;
     const int8_t *cell_p;
@@ -39,6 +39,7 @@ struct DevMesh {
     const int32_t *face_vtx;
     const int32_t *face_cell;
     const int8_t *face_bc;
+    const int32_t *face_opp;  // 3D only: vertex of the left cell's tetrahedron opposite the face
 };
 
 // Per-cell geometry written by the preparation kernel, one 64-byte record per
@@ -75,6 +76,7 @@ struct PrepOut {
 // Problem data as the kernels see it.
 struct DevProblem {
     double a0, a1, bx, by, c, c_sigma;
+    double bz;  // 3D only
     int32_t u_kind;  // 0 sines, 1 polynomial
     double u[10];
 };

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "dgp_common.h"
+#include "dgp3d.h"
 
 namespace dgp {
 
@@ -15,6 +16,12 @@ void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hip
 // a.rows[0 .. n_rows) (all rows in order if a.rows is null), all of degree p;
 // mixed: neighbours may have any degree up to kMaxP (else all have degree p).
 bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, hipStream_t st);
+
+// ---- polyhedral (3D) meshes
+// Geometry, face groups and row counts of every cell, then the tile scan.
+void launch_prep3d(const DevMesh &m, const DevProblem &pr, const Prep3Out &out, hipStream_t st);
+// One wave per element row of degree p (1 or 2), as launch_row2d.
+bool launch_row3d(const Asm3Args &a, int precision, int p, hipStream_t st);
 
 // ---- reduced volume rules
 void launch_cell_poly(const DevMesh &m, const CellGeo *geo, float *feat, double *mom, double *parea, uint8_t *eligible,

@@ -194,6 +194,7 @@ dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dg
     if (!ctx) return DGP_EINVAL;
     if (!ctx->has_mesh) return dgp_fail(ctx, DGP_ESTATE, "dgp_qrule_build before dgp_mesh_upload");
     if (!ctx->has_pattern) return dgp_fail(ctx, DGP_ESTATE, "dgp_qrule_build before dgp_pattern");
+    if (ctx->dim != 2) return dgp_fail(ctx, DGP_EUNSUPPORTED, "reduced rules are built for polygons (2D meshes)");
     if (init != DGP_INIT_NETWORK && init != DGP_INIT_TEMPLATE) return dgp_fail(ctx, DGP_EINVAL, "init = %d", init);
     if (init == DGP_INIT_NETWORK && !ctx->has_mlp)
         return dgp_fail(ctx, DGP_ESTATE, "network initialisation without dgp_mlp_load or dgp_mlp_train");
@@ -227,7 +228,10 @@ dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dg
     for (auto &e : ev) HIPCHK(ctx, hipEventCreate(&e));
     HIPCHK(ctx, hipEventRecord(ev[0], st));
     // element geometry (the bounding boxes) comes from the preparation kernel
-    launch_prep(ctx->dm, DevProblem{1.0, 0.0, 0.0, 0.0, 0.0, 10.0, 0, {}}, ctx->prep, st);
+    DevProblem neutral{};
+    neutral.a0 = 1.0;
+    neutral.c_sigma = 10.0;
+    launch_prep(ctx->dm, neutral, ctx->prep, st);
     launch_cell_poly(ctx->dm, ctx->prep.geo, ctx->qr_feat, ctx->qr_mom, ctx->qr_area, ctx->qr_elig, st);
     HIPCHK(ctx, hipEventRecord(ev[1], st));
     if (init == DGP_INIT_NETWORK) {

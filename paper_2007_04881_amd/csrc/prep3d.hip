@@ -1,0 +1,303 @@
+// Preparation of polyhedral cells, one wave per cell:
+//
+// * geometry in FP64: bounding box and h = diam(kappa), the largest distance
+//   between two vertices (Section 2.2).  Both are taken over the vertices of
+//   the cell's boundary triangles, which include every extreme point of the
+//   polyhedron, so they equal the values over all of its vertices.  The
+//   distinct vertices are collected in an LDS hash set first, so the
+//   distance loop is quadratic in the distinct vertices only;
+// * the block row (Section 3.4, Approach 2: one block per element and per
+//   distinct neighbour): the cell's faces are grouped by neighbour in
+//   ascending order (boundary faces last, one group per boundary code) by
+//   repeated wave minima over the neighbour ids, with each group's rank among
+//   the row's columns and the offset of its block inside the row;
+// * the row's counts (blocks, values, dofs), turned into in-tile prefixes
+//   and tile sums by a one-work-group scan.
+#include "dgp3d.h"
+#include "kernels.h"
+
+namespace dgp {
+
+namespace {
+
+constexpr int WG3 = 256;
+constexpr int CPW = WG3 / 64;             // cells per work-group
+constexpr int FSL = kMaxFaces3D / 64;     // face slots per lane
+constexpr int HSL = kVtxHash3D / 64;      // hash slots per lane in the compaction
+constexpr int kBoundaryKey = 0x7fffff00;  // group key of boundary faces: this | boundary code
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double readlane_dbl(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3Out out) {
+    __shared__ int s_hash[CPW][kVtxHash3D];
+    __shared__ int s_list[CPW][kVtxHash3D];
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int c = blockIdx.x * CPW + w;
+    const bool valid = c < m.n_cells;
+    int64_t fs = 0;
+    int nf = 0, p = 1;
+    if (valid) {
+        fs = m.cell_face_ptr[c];
+        nf = (int)(m.cell_face_ptr[c + 1] - fs);
+        p = m.cell_p[c];
+    }
+    int err = 0;
+    if (nf > kMaxFaces3D) {
+        err = 1;
+        nf = 0;
+    }
+    for (int k = lane; k < kVtxHash3D; k += 64) s_hash[w][k] = -1;
+    __syncthreads();
+
+    // ---- faces: group keys, and their vertices into the hash set
+    int key[FSL], fid[FSL];
+#pragma unroll
+    for (int q = 0; q < FSL; ++q) {
+        const int k = lane + 64 * q;
+        key[q] = INT_MAX;
+        fid[q] = 0;
+        if (k < nf) {
+            const int F = m.cell_face[fs + k];
+            fid[q] = F;
+            const int o = other_cell(m, F, c);
+            key[q] = o >= 0 ? o : (kBoundaryKey | (int)m.face_bc[F]);
+            for (int t = 0; t < 3; ++t) {
+                const int v = m.face_vtx[3 * F + t];
+                int slot = (int)(((unsigned)v * 2654435761u) >> 22) & (kVtxHash3D - 1);
+                bool placed = false;
+                for (int probe = 0; probe < kVtxHash3D; ++probe) {
+                    const int old = atomicCAS(&s_hash[w][slot], -1, v);
+                    if (old == -1 || old == v) {
+                        placed = true;
+                        break;
+                    }
+                    slot = (slot + 1) & (kVtxHash3D - 1);
+                }
+                if (!placed) err = 2;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- compact the distinct vertices into s_list[w][0 .. nu)
+    int mine[HSL];
+    int nmine = 0;
+#pragma unroll
+    for (int k = 0; k < HSL; ++k) {
+        const int v = s_hash[w][lane * HSL + k];
+        mine[k] = v;
+        nmine += v >= 0;
+    }
+    int incl = nmine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    const int nu = __shfl(incl, 63, 64);
+    int pos = incl - nmine;
+#pragma unroll
+    for (int k = 0; k < HSL; ++k)
+        if (mine[k] >= 0) s_list[w][pos++] = mine[k];
+    __syncthreads();
+
+    // ---- bounding box and diameter over the distinct vertices (FP64)
+    constexpr int OWN = kVtxHash3D / 64;
+    double ox[OWN], oy[OWN], oz[OWN];
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+        const int i = lane + 64 * k;
+        ox[k] = oy[k] = oz[k] = 0.0;
+        if (i < nu) {
+            const int v = s_list[w][i];
+            ox[k] = m.x[v];
+            oy[k] = m.y[v];
+            oz[k] = m.z[v];
+            lo[0] = fmin(lo[0], ox[k]);
+            lo[1] = fmin(lo[1], oy[k]);
+            lo[2] = fmin(lo[2], oz[k]);
+            hi[0] = fmax(hi[0], ox[k]);
+            hi[1] = fmax(hi[1], oy[k]);
+            hi[2] = fmax(hi[2], oz[k]);
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = wave_min_d(lo[d]);
+        hi[d] = wave_max_d(hi[d]);
+    }
+    // all pairs: vertex j of chunk k2 is broadcast from its lane, each lane
+    // compares it with the vertices it holds
+    double d2 = 0.0;
+    const int nk = (nu + 63) / 64;
+#pragma unroll
+    for (int k2 = 0; k2 < OWN; ++k2) {
+        if (k2 < nk) {
+            const int cnt = min(64, nu - 64 * k2);
+            for (int l = 0; l < cnt; ++l) {
+                const double xj = readlane_dbl(ox[k2], l), yj = readlane_dbl(oy[k2], l), zj = readlane_dbl(oz[k2], l);
+#pragma unroll
+                for (int k = 0; k < OWN; ++k) {
+                    if (k < nk && lane + 64 * k < nu) {
+                        const double dx = ox[k] - xj, dy = oy[k] - yj, dz = oz[k] - zj;
+                        d2 = fmax(d2, dx * dx + dy * dy + dz * dz);
+                    }
+                }
+            }
+        }
+    }
+    d2 = wave_max_d(d2);
+    err = wave_max_i(err);
+
+    // ---- face groups: neighbours ascending, then boundary codes
+    const int nbc = nb3d(p);
+    int prev = -1, start = 0, ng = 0, nbrs = 0, vsum = 0, below = 0, vbelow = 0;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    while (true) {
+        int kmin = INT_MAX;
+#pragma unroll
+        for (int q = 0; q < FSL; ++q)
+            if (key[q] > prev && key[q] < kmin) kmin = key[q];
+        kmin = wave_min_i(kmin);
+        if (kmin == INT_MAX) break;
+        int cg = 0;
+#pragma unroll
+        for (int q = 0; q < FSL; ++q) {
+            const bool hit = key[q] == kmin;
+            const uint64_t bal = __ballot(hit);
+            if (hit) out.forder[fs + start + cg + __popcll(bal & lt)] = fid[q];
+            cg += __popcll(bal);
+        }
+        FaceGroup g;
+        g.start = start;
+        g.count = cg;
+        if (kmin < kBoundaryKey) {
+            const int o = kmin;
+            const int nbo = nb3d(m.cell_p[o]);
+            const int rank = nbrs + (o > c ? 1 : 0);
+            const int voff = nbc * vsum + (o > c ? nbc * nbc : 0);
+            g.code = o;
+            g.rank_voff = rank | (voff << 8);
+            nbrs += 1;
+            vsum += nbo;
+            if (o < c) {
+                below += 1;
+                vbelow += nbo;
+            }
+        } else {
+            g.code = -(kmin & 0xff);
+            g.rank_voff = 0;
+        }
+        if (lane == 0) out.grp[fs + ng] = g;
+        ng += 1;
+        start += cg;
+        prev = kmin;
+    }
+
+    if (valid && lane == 0) {
+        CellGeo3 g;
+        double box = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            g.lo[d] = lo[d];
+            g.hi[d] = hi[d];
+            box *= hi[d] - lo[d];
+            g.s[d] = 0.0;
+            g.c[d] = 1.0;
+            if (needs_trig(pr)) sincospi(0.5 * (lo[d] + hi[d]), &g.s[d], &g.c[d]);
+        }
+        g.h = sqrt(d2);
+        g.abar = pr.a0;
+        g.sqrt_box = sqrt(box);
+        g.vol = 0.0;
+        g.n_groups = ng;
+        g.pad[0] = g.pad[1] = g.pad[2] = 0;
+        out.geo[c] = g;
+        out.cnt[4 * c + 0] = 1 + nbrs;
+        out.cnt[4 * c + 1] = nbc * (nbc + vsum);
+        out.cnt[4 * c + 2] = nbc;
+        out.cnt[4 * c + 3] = below | ((nbc * vbelow) << 8);
+        if (err || nu >= (kVtxHash3D * 3) / 4) atomicOr(out.err, err ? err : 2);
+    }
+}
+
+// Per-cell counts -> in-tile exclusive prefixes (in place) and tile sums, then
+// an exclusive scan of the tile sums with the totals after the last tile.  One
+// work-group; each thread owns a run of consecutive tiles.
+__global__ void __launch_bounds__(1024) k_scan3d(int n_cells, int32_t *__restrict__ cnt,
+                                                 int64_t *__restrict__ tile_sum, int64_t *__restrict__ tile_off) {
+    __shared__ int64_t sh[3][1024];
+    const int n_tiles = (n_cells + kPrepTile - 1) / kPrepTile;
+    const int t = threadIdx.x;
+    const int per = (n_tiles + 1023) / 1024;
+    const int a = t * per, b = min(a + per, n_tiles);
+    int64_t run[3] = {0, 0, 0};
+    for (int i = a; i < b; ++i) {
+        int acc[3] = {0, 0, 0};
+        const int c1 = min(n_cells, (i + 1) * kPrepTile);
+        for (int c = i * kPrepTile; c < c1; ++c)
+            for (int q = 0; q < 3; ++q) {
+                const int v = cnt[4 * c + q];
+                cnt[4 * c + q] = acc[q];
+                acc[q] += v;
+            }
+        for (int q = 0; q < 3; ++q) {
+            tile_sum[3 * i + q] = acc[q];
+            run[q] += acc[q];
+        }
+    }
+    for (int q = 0; q < 3; ++q) sh[q][t] = run[q];
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v[3] = {0, 0, 0};
+        if (t >= off)
+            for (int q = 0; q < 3; ++q) v[q] = sh[q][t - off];
+        __syncthreads();
+        for (int q = 0; q < 3; ++q) sh[q][t] += v[q];
+        __syncthreads();
+    }
+    int64_t acc[3];
+    for (int q = 0; q < 3; ++q) acc[q] = sh[q][t] - run[q];
+    for (int i = a; i < b; ++i)
+        for (int q = 0; q < 3; ++q) {
+            tile_off[3 * i + q] = acc[q];
+            acc[q] += tile_sum[3 * i + q];
+        }
+    if (t == 1023)
+        for (int q = 0; q < 3; ++q) tile_off[3 * n_tiles + q] = sh[q][1023];
+}
+
+void launch_prep3d(const DevMesh &m, const DevProblem &pr, const Prep3Out &out, hipStream_t st) {
+    hipLaunchKernelGGL(k_prep3d, dim3((m.n_cells + CPW - 1) / CPW), dim3(WG3), 0, st, m, pr, out);
+    hipLaunchKernelGGL(k_scan3d, dim3(1), dim3(1024), 0, st, m.n_cells, out.cnt, out.tile_sum, out.tile_off);
+}
+
+}  // namespace dgp

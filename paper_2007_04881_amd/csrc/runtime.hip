@@ -115,10 +115,13 @@ dgp_status dgp_set_stream(dgp_ctx *ctx, void *hip_stream) {
 
 const char *dgp_last_error(const dgp_ctx *ctx) { return ctx ? ctx->err : "null context"; }
 
+static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m);
+
 dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     if (!ctx || !m) return DGP_EINVAL;
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    if (m->dim != 2) return fail(ctx, DGP_EUNSUPPORTED, "dim %d: this version assembles 2D meshes", m->dim);
+    if (m->dim == 3) return upload3d(ctx, m);
+    if (m->dim != 2) return fail(ctx, DGP_EUNSUPPORTED, "dim %d", m->dim);
     if (m->n_cells <= 0 || m->n_vertices <= 0 || m->n_faces <= 0)
         return fail(ctx, DGP_EINVAL, "empty mesh (cells %lld, vertices %lld, faces %lld)", (long long)m->n_cells,
                     (long long)m->n_vertices, (long long)m->n_faces);
@@ -169,6 +172,7 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     }
     free_mesh(ctx);
     ctx->dim = 2;
+    ctx->n_cell_face = nnz_v;
     ctx->n_cells = N;
     ctx->n_faces = F;
     ctx->n_vertices = V;
@@ -176,6 +180,7 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     ctx->p_uniform = pmin == pmax ? pmin : -1;
     ctx->p_max = pmax;
     DevMesh &d = ctx->dm;
+    d = DevMesh{};
     d.n_cells = (int32_t)N;
     d.n_faces = (int32_t)F;
     d.n_vertices = (int32_t)V;
@@ -241,6 +246,137 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     return DGP_OK;
 }
 
+// Polyhedral mesh: cells are unions of tetrahedra (4 ids each), faces are
+// triangles with the opposite vertex of the left cell's tetrahedron.
+static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
+    if (m->n_cells <= 0 || m->n_vertices <= 0 || m->n_faces <= 0)
+        return fail(ctx, DGP_EINVAL, "empty mesh (cells %lld, vertices %lld, faces %lld)", (long long)m->n_cells,
+                    (long long)m->n_vertices, (long long)m->n_faces);
+    if (m->n_cells > INT32_MAX / 2 || m->n_faces > INT32_MAX / 2 || m->n_vertices > INT32_MAX / 2)
+        return fail(ctx, DGP_EUNSUPPORTED, "mesh too large for 32-bit ids");
+    if (!m->x || !m->y || !m->z || !m->cell_ptr || !m->cell_vtx || !m->cell_p || !m->cell_face_ptr ||
+        !m->cell_face || !m->face_vtx || !m->face_cell || !m->face_bc || !m->face_opp)
+        return fail(ctx, DGP_EINVAL, "null mesh array");
+    const int64_t N = m->n_cells, F = m->n_faces, V = m->n_vertices;
+    if (m->cell_ptr[0] != 0 || m->cell_face_ptr[0] != 0) return fail(ctx, DGP_EMESH, "cell_ptr[0] or cell_face_ptr[0] != 0");
+    int pmin = 99, pmax = -1;
+    for (int64_t c = 0; c < N; ++c) {
+        const int64_t s = m->cell_ptr[c], e = m->cell_ptr[c + 1];
+        if (e - s < 4 || (e - s) % 4 || s % 4)
+            return fail(ctx, DGP_EMESH, "cell %lld: %lld tetrahedron vertex ids (need a positive multiple of 4)",
+                        (long long)c, (long long)(e - s));
+        for (int64_t k = s; k < e; ++k)
+            if (m->cell_vtx[k] < 0 || m->cell_vtx[k] >= V)
+                return fail(ctx, DGP_EMESH, "cell %lld: vertex id %d out of range", (long long)c, m->cell_vtx[k]);
+        const int p = m->cell_p[c];
+        if (p < 1 || p > kMaxP3D) return fail(ctx, DGP_EUNSUPPORTED, "3D cell %lld has degree %d (1..%d)", (long long)c, p, kMaxP3D);
+        pmin = p < pmin ? p : pmin;
+        pmax = p > pmax ? p : pmax;
+        const int64_t fs = m->cell_face_ptr[c], fe = m->cell_face_ptr[c + 1];
+        if (fe - fs < 4) return fail(ctx, DGP_EMESH, "cell %lld has %lld faces", (long long)c, (long long)(fe - fs));
+        if (fe - fs > kMaxFaces3D)
+            return fail(ctx, DGP_EUNSUPPORTED, "cell %lld has %lld faces (at most %d)", (long long)c, (long long)(fe - fs),
+                        kMaxFaces3D);
+        for (int64_t k = fs; k < fe; ++k) {
+            const int32_t f = m->cell_face[k];
+            if (f < 0 || f >= F) return fail(ctx, DGP_EMESH, "cell %lld: face id %d out of range", (long long)c, f);
+            if (m->face_cell[2 * f] != c && m->face_cell[2 * f + 1] != c)
+                return fail(ctx, DGP_EMESH, "face %d is not adjacent to cell %lld", f, (long long)c);
+        }
+    }
+    for (int64_t f = 0; f < F; ++f) {
+        const int32_t l = m->face_cell[2 * f], r = m->face_cell[2 * f + 1];
+        const int8_t bc = m->face_bc[f];
+        if (l < 0 || l >= N || r < -1 || r >= N || r == l)
+            return fail(ctx, DGP_EMESH, "face %lld: bad cells (%d, %d)", (long long)f, l, r);
+        if ((r < 0) != (bc != 0) || bc < 0 || bc > 2)
+            return fail(ctx, DGP_EMESH, "face %lld: boundary code %d inconsistent with cells", (long long)f, bc);
+        const int32_t o = m->face_opp[f];
+        if (o < 0 || o >= V) return fail(ctx, DGP_EMESH, "face %lld: opposite vertex out of range", (long long)f);
+        for (int t = 0; t < 3; ++t) {
+            const int32_t v = m->face_vtx[3 * f + t];
+            if (v < 0 || v >= V || v == o) return fail(ctx, DGP_EMESH, "face %lld: bad vertex %d", (long long)f, v);
+        }
+    }
+    free_mesh(ctx);
+    const int64_t n_cv = m->cell_ptr[N], n_cf = m->cell_face_ptr[N];
+    ctx->dim = 3;
+    ctx->n_cells = N;
+    ctx->n_faces = F;
+    ctx->n_vertices = V;
+    ctx->n_cell_vtx = n_cv;
+    ctx->n_cell_face = n_cf;
+    ctx->p_uniform = pmin == pmax ? pmin : -1;
+    ctx->p_max = pmax;
+    DevMesh &d = ctx->dm;
+    d = DevMesh{};
+    d.n_cells = (int32_t)N;
+    d.n_faces = (int32_t)F;
+    d.n_vertices = (int32_t)V;
+    dgp_status st;
+#define UP(arr, n, field)                                         \
+    if ((st = upload(ctx, m->arr, (n), &d.field)) != DGP_OK) { \
+        free_mesh(ctx);                                           \
+        return st;                                                \
+    }
+    UP(x, V, x)
+    UP(y, V, y)
+    UP(z, V, z)
+    UP(cell_ptr, N + 1, cell_ptr)
+    UP(cell_vtx, n_cv, cell_vtx)
+    UP(cell_p, N, cell_p)
+    UP(cell_face_ptr, N + 1, cell_face_ptr)
+    UP(cell_face, n_cf, cell_face)
+    UP(face_vtx, 3 * F, face_vtx)
+    UP(face_cell, 2 * F, face_cell)
+    UP(face_bc, F, face_bc)
+    UP(face_opp, F, face_opp)
+#undef UP
+    const int64_t nnzb_max = N + n_cf;
+    ctx->n_tiles = (int)((N + kPrepTile - 1) / kPrepTile);
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t o_geo = 0;
+    const size_t o_ord = o_geo + al(sizeof(CellGeo3) * (size_t)N);
+    const size_t o_grp = o_ord + al(sizeof(int32_t) * (size_t)n_cf);
+    const size_t o_cnt = o_grp + al(sizeof(FaceGroup) * (size_t)n_cf);
+    const size_t o_tile = o_cnt + al(sizeof(int32_t) * 4 * (size_t)N);
+    const size_t o_off = o_tile + al(sizeof(int64_t) * 3 * (size_t)ctx->n_tiles);
+    const size_t o_err = o_off + al(sizeof(int64_t) * 3 * (size_t)(ctx->n_tiles + 1));
+    const size_t work_bytes = o_err + 256;
+    if (hipMalloc(&ctx->row_ptr, sizeof(int64_t) * (N + 1)) != hipSuccess ||
+        hipMalloc(&ctx->col_idx, sizeof(int32_t) * nnzb_max) != hipSuccess ||
+        hipMalloc(&ctx->val_ptr, sizeof(int64_t) * (nnzb_max + 1)) != hipSuccess ||
+        hipMalloc(&ctx->dof_ptr, sizeof(int64_t) * (N + 1)) != hipSuccess ||
+        hipMalloc(&ctx->work, work_bytes) != hipSuccess) {
+        free_mesh(ctx);
+        return fail(ctx, DGP_ENOMEM, "device allocation failed");
+    }
+    HIPCHK(ctx, hipMemset(ctx->work, 0, work_bytes));
+    char *b = static_cast<char *>(ctx->work);
+    ctx->prep3.geo = reinterpret_cast<CellGeo3 *>(b + o_geo);
+    ctx->prep3.forder = reinterpret_cast<int32_t *>(b + o_ord);
+    ctx->prep3.grp = reinterpret_cast<FaceGroup *>(b + o_grp);
+    ctx->prep3.cnt = reinterpret_cast<int32_t *>(b + o_cnt);
+    ctx->prep3.tile_sum = reinterpret_cast<int64_t *>(b + o_tile);
+    ctx->prep3.tile_off = reinterpret_cast<int64_t *>(b + o_off);
+    ctx->prep3.err = reinterpret_cast<int32_t *>(b + o_err);
+    if (pmin != pmax) {
+        std::vector<int32_t> rows((size_t)N);
+        int64_t cnt[kMaxP + 2] = {};
+        for (int64_t c = 0; c < N; ++c) cnt[m->cell_p[c] + 1] += 1;
+        for (int p = 1; p <= kMaxP + 1; ++p) cnt[p] += cnt[p - 1];
+        for (int p = 0; p <= kMaxP + 1; ++p) ctx->rows_off[p] = cnt[p];
+        for (int64_t c = 0; c < N; ++c) rows[(size_t)cnt[m->cell_p[c]]++] = (int32_t)c;
+        if (hipMalloc(&ctx->rows_by_p, sizeof(int32_t) * (size_t)N) != hipSuccess) {
+            free_mesh(ctx);
+            return fail(ctx, DGP_ENOMEM, "row groups");
+        }
+        HIPCHK(ctx, hipMemcpy(ctx->rows_by_p, rows.data(), sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice));
+    }
+    ctx->has_mesh = true;
+    return DGP_OK;
+}
+
 static DevProblem neutral_problem() {
     DevProblem d{};
     d.a0 = 1.0;
@@ -251,6 +387,13 @@ static DevProblem neutral_problem() {
 static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
                                int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed);
 
+static void launch_prep_any(dgp_ctx *ctx, const DevProblem &dp, hipStream_t st) {
+    if (ctx->dim == 3)
+        launch_prep3d(ctx->dm, dp, ctx->prep3, st);
+    else
+        launch_prep(ctx->dm, dp, ctx->prep, st);
+}
+
 dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
     if (!ctx || !out) return DGP_EINVAL;
     if (!ctx->has_mesh) return fail(ctx, DGP_ESTATE, "dgp_pattern before dgp_mesh_upload");
@@ -260,9 +403,15 @@ dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
     dgp_status st = enqueue_step(ctx, neutral_problem(), DGP_F64, DGP_RULE_PLAIN, 0, 1, nullptr, nullptr, ctx->stream, false);
     if (st) return st;
     int64_t tot[3];
-    HIPCHK(ctx, hipMemcpyAsync(tot, ctx->prep.tile_off + 3 * ctx->n_tiles, sizeof(tot), hipMemcpyDeviceToHost,
-                               ctx->stream));
+    const int64_t *toff = ctx->dim == 3 ? ctx->prep3.tile_off : ctx->prep.tile_off;
+    HIPCHK(ctx, hipMemcpyAsync(tot, toff + 3 * ctx->n_tiles, sizeof(tot), hipMemcpyDeviceToHost, ctx->stream));
+    int32_t err3 = 0;
+    if (ctx->dim == 3)
+        HIPCHK(ctx, hipMemcpyAsync(&err3, ctx->prep3.err, sizeof(err3), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (err3)
+        return fail(ctx, DGP_EUNSUPPORTED, "a polyhedron exceeds the preparation kernel's limits (%d faces, %d distinct surface vertices)",
+                    kMaxFaces3D, (kVtxHash3D * 3) / 4);
     ctx->nnzb = tot[0];
     ctx->n_vals = tot[1];
     ctx->n_dofs = tot[2];
@@ -296,6 +445,7 @@ static DevProblem to_dev(const dgp_problem *p) {
     d.a1 = p->a1;
     d.bx = p->b[0];
     d.by = p->b[1];
+    d.bz = p->b[2];
     d.c = p->c;
     d.c_sigma = p->c_sigma;
     d.u_kind = p->u_kind;
@@ -312,6 +462,10 @@ static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int
     if (!(prob->c_sigma >= 0.0)) return fail(ctx, DGP_EINVAL, "c_sigma must be >= 0");
     if (rule_mode != DGP_RULE_PLAIN && rule_mode != DGP_RULE_REDUCED)
         return fail(ctx, DGP_EINVAL, "rule_mode %d", rule_mode);
+    if (ctx->dim == 3) {
+        if (prob->a1 != 0.0) return fail(ctx, DGP_EUNSUPPORTED, "3D meshes take a constant diffusion coefficient (a1 = 0)");
+        if (rule_mode != DGP_RULE_PLAIN) return fail(ctx, DGP_EUNSUPPORTED, "reduced rules are for 2D meshes");
+    }
     if (rule_mode == DGP_RULE_REDUCED) {
         if (!ctx->has_qrule) return fail(ctx, DGP_ESTATE, "reduced rules requested before dgp_qrule_build");
         if (prob->a1 != 0.0)
@@ -321,8 +475,45 @@ static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int
     return DGP_OK;
 }
 
+static dgp_status launch_assembly3d(dgp_ctx *ctx, const DevProblem &dp, int precision, int values, int write_pattern,
+                                    void *vals, void *rhs, hipStream_t st) {
+    Asm3Args a;
+    a.m = ctx->dm;
+    a.pr = dp;
+    a.geo = ctx->prep3.geo;
+    a.forder = ctx->prep3.forder;
+    a.grp = ctx->prep3.grp;
+    a.cnt = ctx->prep3.cnt;
+    a.tile_off = ctx->prep3.tile_off;
+    a.row_ptr = ctx->row_ptr;
+    a.col_idx = ctx->col_idx;
+    a.val_ptr = ctx->val_ptr;
+    a.dof_ptr = ctx->dof_ptr;
+    a.vals = vals;
+    a.rhs = rhs;
+    a.values = values;
+    a.write_pattern = write_pattern;
+    a.rows = nullptr;
+    a.n_rows = (int32_t)ctx->n_cells;
+    if (ctx->p_uniform > 0) {
+        if (!launch_row3d(a, precision, ctx->p_uniform, st))
+            return fail(ctx, DGP_EUNSUPPORTED, "no 3D kernel for precision %d, p %d", precision, ctx->p_uniform);
+    } else {
+        for (int p = 1; p <= kMaxP3D; ++p) {
+            const int64_t n = ctx->rows_off[p + 1] - ctx->rows_off[p];
+            if (n == 0) continue;
+            a.rows = ctx->rows_by_p + ctx->rows_off[p];
+            a.n_rows = (int32_t)n;
+            if (!launch_row3d(a, precision, p, st))
+                return fail(ctx, DGP_EUNSUPPORTED, "no 3D kernel for precision %d, p %d", precision, p);
+        }
+    }
+    return DGP_OK;
+}
+
 static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
                                   int write_pattern, void *vals, void *rhs, hipStream_t st) {
+    if (ctx->dim == 3) return launch_assembly3d(ctx, dp, precision, values, write_pattern, vals, rhs, st);
     AsmArgs a;
     a.m = ctx->dm;
     a.pr = dp;
@@ -365,7 +556,7 @@ static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precis
 static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
                                int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed) {
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
-    launch_prep(ctx->dm, dp, ctx->prep, st);
+    launch_prep_any(ctx, dp, st);
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
     dgp_status s = launch_assembly(ctx, dp, precision, rule_mode, values, write_pattern, vals, rhs, st);
     if (s) return s;
@@ -449,7 +640,7 @@ dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assem
     HIPCHK(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
-    for (int i = 0; i < reps; ++i) launch_prep(ctx->dm, ctx->last_pr, ctx->prep, st);
+    for (int i = 0; i < reps; ++i) launch_prep_any(ctx, ctx->last_pr, st);
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
     for (int i = 0; i < reps; ++i) {
         dgp_status s = launch_assembly(ctx, ctx->last_pr, ctx->last_precision, ctx->last_rule, 1, 0, ctx->last_vals,

@@ -43,20 +43,24 @@ def block_errors(g, vals_ref, rhs_ref, pat, rows=None):
     rows = range(len(pat.row_ptr) - 1) if rows is None else rows
     worst_b = 0.0
     worst_r = 0.0
+    # with sampled rows the oracle leaves the other rows NaN: scale by the sampled ones
+    rhs_scale = max(np.abs(rhs_ref[pat.dof_ptr[r]:pat.dof_ptr[r + 1]]).max() for r in rows)
     for r in rows:
         for k in range(pat.row_ptr[r], pat.row_ptr[r + 1]):
             sl = slice(pat.val_ptr[k], pat.val_ptr[k + 1])
             ref = vals_ref[sl]
             nrm = np.linalg.norm(ref)
             err = np.linalg.norm(g["vals"][sl] - ref)
+            assert not np.isnan(err), f"block {k} of row {r} is NaN"
             worst_b = max(worst_b, err / nrm if nrm > 0 else err)
         sl = slice(pat.dof_ptr[r], pat.dof_ptr[r + 1])
         ref = rhs_ref[sl]
+        assert not np.isnan(ref).any(), f"oracle load of row {r} missing"
         nrm = np.linalg.norm(ref)
         err = np.linalg.norm(g["rhs"][sl] - ref)
+        assert not np.isnan(err), f"load of row {r} is NaN"
         # a row whose load vanishes (g_D = 0, f ~ 0) is compared in absolute terms
-        scale = max(nrm, 1e-300)
-        worst_r = max(worst_r, err / scale if nrm > 1e-10 * np.abs(rhs_ref).max() else err / np.abs(rhs_ref).max())
+        worst_r = max(worst_r, err / nrm if nrm > 1e-10 * rhs_scale else err / rhs_scale)
     return worst_b, worst_r
 
 
