@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-KERNEL_SOURCES = ["assemble_row.hip", "asm_common.h", "dgp_common.h", "rules_data.h"]
+KERNEL_SOURCES = ["assemble_row.hip", "asm_common.h", "dgp_common.h", "rules_data.h", "wave.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_row2d_p2_f32_voronoi16384.json")
 
 
@@ -183,6 +183,28 @@ def polyhedra_study(D, torch, steps, warmup):
     return out
 
 
+def traffic_probe(D, torch):
+    """A short program for rocprofv3 --pmc: the assembly kernel's dispatches and
+    a copy of known size to scale the counters by."""
+    from meshgen import config_mesh, problem_params
+    mesh, params = config_mesh(2), problem_params(2)
+    ctx = D.Context(0)
+    ctx.upload(mesh)
+    ctx.pattern()
+    vals, rhs = ctx.outputs(D.F32)
+    for _ in range(10):
+        ctx.run(params, D.F32, vals, rhs)
+    torch.cuda.synchronize()
+    x = torch.empty(16 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 64 MiB
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    for _ in range(10):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    ctx.close()
+    log("traffic probe done")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +213,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-rule study")
     ap.add_argument("--no-3d", action="store_true", help="skip the polyhedral (3D) workload")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="for HBM counter runs: 10 whole steps of the headline workload, then 10 copies of a "
+                         "64 MiB tensor (the copy calibrates FETCH_SIZE / WRITE_SIZE); prints no JSON")
     ap.add_argument("--train-polygons", type=int, default=1_000_000)
     ap.add_argument("--train-epochs", type=int, default=30)
     args = ap.parse_args()
@@ -203,6 +228,10 @@ def main():
     import torch
     import paper_2007_04881_amd as D
     from meshgen import config_mesh, problem_params
+
+    if args.traffic_probe:
+        traffic_probe(D, torch)
+        return
 
     log("16,384-cell mesh")
     mesh = config_mesh(2)

@@ -153,25 +153,35 @@ __device__ __forceinline__ void exact3(const DevProblem &pr, const Trig3 &t, con
 }
 
 // unnormalised basis values u_i = P_a P_b P_c and normal derivatives
-// g_i = sum_d nc_d dP..., nc_d = n_d (2 / h_d), of the first N functions
+// g_i = sum_d nc_d d/dxi_d (P_a P_b P_c), nc_d = n_d (2 / h_d), of the first N
+// functions (degree <= 2: P_1 = t, P_2 = (3t^2 - 1)/2, P_2' = 3t)
 template <typename T, int N>
 __device__ __forceinline__ void basis3(const T *xi, const T *nc, T *u, T *g) {
-    T P[3][3], D[3][3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        P[d][0] = T(1);
-        P[d][1] = xi[d];
-        P[d][2] = T(1.5) * xi[d] * xi[d] - T(0.5);
-        D[d][0] = T(0);
-        D[d][1] = T(1);
-        D[d][2] = T(3) * xi[d];
+    static_assert(N == 1 || N == 4 || N == 10, "degree <= 2");
+    const T x = xi[0], y = xi[1], z = xi[2];
+    u[0] = T(1);
+    g[0] = T(0);
+    if (N > 1) {
+        u[1] = x;
+        u[2] = y;
+        u[3] = z;
+        g[1] = nc[0];
+        g[2] = nc[1];
+        g[3] = nc[2];
     }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const int a = exp3(i, 0), b = exp3(i, 1), c = exp3(i, 2);
-        u[i] = P[0][a] * P[1][b] * P[2][c];
-        g[i] = nc[0] * D[0][a] * P[1][b] * P[2][c] + nc[1] * P[0][a] * D[1][b] * P[2][c] +
-               nc[2] * P[0][a] * P[1][b] * D[2][c];
+    if (N > 4) {
+        u[4] = T(1.5) * x * x - T(0.5);
+        u[5] = x * y;
+        u[6] = x * z;
+        u[7] = T(1.5) * y * y - T(0.5);
+        u[8] = y * z;
+        u[9] = T(1.5) * z * z - T(0.5);
+        g[4] = T(3) * x * nc[0];
+        g[5] = nc[0] * y + nc[1] * x;
+        g[6] = nc[0] * z + nc[2] * x;
+        g[7] = T(3) * y * nc[1];
+        g[8] = nc[1] * z + nc[2] * y;
+        g[9] = T(3) * z * nc[2];
     }
 }
 
@@ -225,7 +235,7 @@ __device__ __forceinline__ void row_begin(const Asm3Args &A, int c, Row3 &R) {
     R.isq = uniform(1.0 / G.sqrt_box);
     R.fs = A.m.cell_face_ptr[c];
     R.ng = G.n_groups;
-    const int t0 = c / kPrepTile;
+    const int t0 = c / kPrepTile3D;
     const int4 cr = reinterpret_cast<const int4 *>(A.cnt)[c];
     R.pre_b = A.tile_off[3 * t0] + cr.x;
     R.pre_v = A.tile_off[3 * t0 + 1] + cr.y;
@@ -419,7 +429,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
             A.row_ptr[c] = pre_b;
             A.dof_ptr[c] = pre_d;
             if (c == m.n_cells - 1) {
-                const int n_tiles = (m.n_cells + kPrepTile - 1) / kPrepTile;
+                const int n_tiles = (m.n_cells + kPrepTile3D - 1) / kPrepTile3D;
                 const int64_t nnzb = A.tile_off[3 * n_tiles];
                 A.row_ptr[c + 1] = nnzb;
                 A.val_ptr[nnzb] = A.tile_off[3 * n_tiles + 1];
@@ -430,14 +440,95 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
     if (!A.values) return;
     const Trig3 tc = row_trig(G, R);
 
-    // ---- face terms, group by group.  Two passes over a group's points keep
-    // the live accumulators small: the cross block (interior groups), then the
-    // group's part of the diagonal block and of the load, reduced at once into
-    // the entry each lane owns (dself, fself).
+    // ---- face terms in two sweeps over the groups, so that the cross block
+    // and the diagonal block are never live together: first every interior
+    // group's cross block (reduced and written after the group), then the face
+    // part of the diagonal block (packed) and of the load over all groups,
+    // reduced once.
     const double a = pr.a0;
     const double pen_r = uniform(G.abar * (P * P) / G.h);
-    double dself = 0.0, fself = 0.0;
     T *vals = static_cast<T *>(A.vals);
+    for (int gi = 0; gi < ng; ++gi) {
+        const FaceGroup gr = A.grp[fs + gi];
+        const int code = gr.code;
+        if (code < 0) continue;
+        const int npts = DGP_TRI4_N * gr.count;
+        const int32_t *gface = A.forder + fs + gr.start;
+        const CellGeo3 &Gn = A.geo[code];
+        const int pn = m.cell_p[code];
+        const int nbo = nb3d(pn);
+        double ncx[3], nctr[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ncx[d] = uniform(2.0 / (Gn.hi[d] - Gn.lo[d]));
+            nctr[d] = uniform(0.5 * (Gn.lo[d] + Gn.hi[d]));
+        }
+        const double nisq = uniform(1.0 / Gn.sqrt_box);
+        const double pen = uniform(pr.c_sigma * fmax(pen_r, Gn.abar * (pn * pn) / Gn.h));
+        T xa0[64], xa1[64];
+#pragma unroll
+        for (int k = 0; k < NX0; ++k) xa0[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < NX1; ++k) xa1[k] = T(0);
+        for (int pi = lane; pi < npts; pi += 64) {
+            FacePt fp;
+            face_point(m, c, gface, pi, fp);
+            const double bn = pr.bx * fp.n[0] + pr.by * fp.n[1] + pr.bz * fp.n[2];
+            const T tha = T(-fp.w * 0.5 * a), ths = T(fp.w * (pen - (bn < 0.0 ? bn : 0.0)));
+            T xi[3], nc[3], u[NB], g[NB], v[NBN], gv[NBN];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                xi[d] = T((fp.x[d] - ctr[d]) * cx[d]);
+                nc[d] = T(fp.n[d] * cx[d]);
+            }
+            basis3<T, NB>(xi, nc, u, g);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                xi[d] = T((fp.x[d] - nctr[d]) * ncx[d]);
+                nc[d] = T(fp.n[d] * ncx[d]);
+            }
+            basis3<T, NBN>(xi, nc, v, gv);
+            // X_ij += u_i (ha g'_j - hs v_j) + g_i (-ha v_j)   (u_0 = 1, g_0 = 0)
+#pragma unroll
+            for (int j = 0; j < NBN; ++j) {
+                const T tx = tha * gv[j] - ths * v[j];
+                const T ux = -tha * v[j];
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const int e = i * NBN + j;
+                    T &acc = e < 64 ? xa0[e < 64 ? e : 0] : xa1[e >= 64 ? e - 64 : 0];
+                    if (i == 0) {
+                        acc += tx;
+                    } else {
+                        acc = fma(u[i], tx, acc);
+                        acc = fma(g[i], ux, acc);
+                    }
+                }
+            }
+        }
+        // entry e = i * NBN + j of the degree-2 neighbour basis; the neighbour's
+        // first nbo functions are its basis of degree p_n
+        WaveRS<T, 32, NX0>::run(xa0, lane);
+        if (NX1 > 0) WaveRS<T, 32, (NX1 > 0 ? NX1 : 1)>::run(xa1, lane);
+        const int64_t base = pre_v + (gr.rank_voff >> 8);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int e = lane + 64 * r;
+            if (e < NXE) {
+                const int i = e / NBN, j = e % NBN;
+                if (j < nbo) {
+                    const double sum = double(r == 0 ? xa0[0] : xa1[0]);
+                    vals[base + i * nbo + j] = T(sum * (c_norm3[i] * isq) * (c_norm3[j] * nisq));
+                }
+            }
+        }
+    }
+
+    T dp[64], rf[64];
+#pragma unroll
+    for (int k = 0; k < NPK; ++k) dp[k] = T(0);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) rf[k] = T(0);
     for (int gi = 0; gi < ng; ++gi) {
         const FaceGroup gr = A.grp[fs + gi];
         const int code = gr.code;
@@ -449,68 +540,8 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
         if (inner) {
             const CellGeo3 &Gn = A.geo[code];
             const int pn = m.cell_p[code];
-            const int nbo = nb3d(pn);
-            double ncx[3], nctr[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                ncx[d] = uniform(2.0 / (Gn.hi[d] - Gn.lo[d]));
-                nctr[d] = uniform(0.5 * (Gn.lo[d] + Gn.hi[d]));
-            }
-            const double nisq = uniform(1.0 / Gn.sqrt_box);
             pen = uniform(pr.c_sigma * fmax(pen_r, Gn.abar * (pn * pn) / Gn.h));
-            T xa0[64], xa1[64];
-#pragma unroll
-            for (int k = 0; k < 64; ++k) xa0[k] = xa1[k] = T(0);
-            for (int pi = lane; pi < npts; pi += 64) {
-                FacePt fp;
-                face_point(m, c, gface, pi, fp);
-                const double bn = pr.bx * fp.n[0] + pr.by * fp.n[1] + pr.bz * fp.n[2];
-                const T tha = T(-fp.w * theta * a), ths = T(fp.w * (pen - (bn < 0.0 ? bn : 0.0)));
-                T xi[3], nc[3], u[NB], g[NB], nxi[3], nnc[3], v[NBN], gv[NBN];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    xi[d] = T((fp.x[d] - ctr[d]) * cx[d]);
-                    nc[d] = T(fp.n[d] * cx[d]);
-                    nxi[d] = T((fp.x[d] - nctr[d]) * ncx[d]);
-                    nnc[d] = T(fp.n[d] * ncx[d]);
-                }
-                basis3<T, NB>(xi, nc, u, g);
-                basis3<T, NBN>(nxi, nnc, v, gv);
-#pragma unroll
-                for (int j = 0; j < NBN; ++j) {
-                    const T tx = tha * gv[j] - ths * v[j];
-                    const T ux = -tha * v[j];
-#pragma unroll
-                    for (int i = 0; i < NB; ++i) {
-                        const int e = i * NBN + j;
-                        if (e < 64)
-                            xa0[e] += u[i] * tx + g[i] * ux;
-                        else
-                            xa1[e - 64] += u[i] * tx + g[i] * ux;
-                    }
-                }
-            }
-            // entry e = i * NBN + j of the degree-2 neighbour basis; the neighbour's
-            // first nbo functions are its basis of degree p_n
-            WaveRS<T, 32, NX0>::run(xa0, lane);
-            if (NX1 > 0) WaveRS<T, 32, (NX1 > 0 ? NX1 : 1)>::run(xa1, lane);
-            const int64_t base = pre_v + (gr.rank_voff >> 8);
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int e = lane + 64 * r;
-                if (e < NXE) {
-                    const int i = e / NBN, j = e % NBN;
-                    if (j < nbo) {
-                        const double sum = double(r == 0 ? xa0[0] : xa1[0]);
-                        vals[base + i * nbo + j] = T(sum * (c_norm3[i] * isq) * (c_norm3[j] * nisq));
-                    }
-                }
-            }
         }
-        // the group's part of the diagonal block (not on Neumann faces) and of the load
-        T dp[64], rf[64];
-#pragma unroll
-        for (int k = 0; k < 64; ++k) dp[k] = rf[k] = T(0);
         for (int pi = lane; pi < npts; pi += 64) {
             FacePt fp;
             face_point(m, c, gface, pi, fp);
@@ -524,13 +555,22 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
             }
             basis3<T, NB>(xi, nc, u, g);
             if (code != -2) {
+                // D_ij += u_i (hs u_j + ha g_j) + g_i (ha u_j), i <= j
                 const T tha = T(ha), ths = T(hs);
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
                     const T tj = ths * u[j] + tha * g[j];
                     const T sj = tha * u[j];
 #pragma unroll
-                    for (int i = 0; i <= j; ++i) dp[pk(NB, i, j)] += u[i] * tj + g[i] * sj;
+                    for (int i = 0; i <= j; ++i) {
+                        T &acc = dp[pk(NB, i, j)];
+                        if (i == 0) {
+                            acc += tj;
+                        } else {
+                            acc = fma(u[i], tj, acc);
+                            acc = fma(g[i], sj, acc);
+                        }
+                    }
                 }
             }
             if (!inner) {
@@ -539,23 +579,18 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
                 if (code == -1) {
                     const T r0 = T(ha * ue), r1 = T(hs * ue);
 #pragma unroll
-                    for (int i = 0; i < NB; ++i) rf[i] += g[i] * r0 + u[i] * r1;
+                    for (int i = 0; i < NB; ++i) rf[i] = fma(g[i], r0, fma(u[i], r1, rf[i]));
                 } else {
                     const T gn = T(fp.w * a * (gu[0] * fp.n[0] + gu[1] * fp.n[1] + gu[2] * fp.n[2]));
 #pragma unroll
-                    for (int i = 0; i < NB; ++i) rf[i] += u[i] * gn;
+                    for (int i = 0; i < NB; ++i) rf[i] = fma(u[i], gn, rf[i]);
                 }
             }
         }
-        if (code != -2) {
-            WaveRS<T, 32, NPK>::run(dp, lane);
-            dself += double(dp[0]);
-        }
-        if (!inner) {
-            WaveRS<T, 32, NB>::run(rf, lane);
-            fself += double(rf[0]);
-        }
     }
+    WaveRS<T, 32, NPK>::run(dp, lane);
+    WaveRS<T, 32, NB>::run(rf, lane);
+    const double dself = double(dp[0]), fself = double(rf[0]);
 
     // ---- face part added to the element part of the diagonal block and the load
 #pragma unroll

@@ -18,6 +18,7 @@ namespace dgp {
 constexpr int kMaxP3D = 2;         // 3D kernels are built for p = 1, 2
 constexpr int kMaxFaces3D = 1024;  // boundary triangles of one polyhedron handled by the preparation kernel
 constexpr int kVtxHash3D = 1024;   // LDS hash slots per polyhedron for its distinct surface vertices
+constexpr int kPrepTile3D = 4;     // cells per tile of the 3D row offsets (one preparation work-group)
 
 __host__ __device__ constexpr int nb3d(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
@@ -50,7 +51,7 @@ struct Prep3Out {
     CellGeo3 *geo;
     int32_t *forder;    // [cell-face entries] face ids grouped by neighbour, same ranges as cell_face
     FaceGroup *grp;     // [cell-face entries] the cell's groups, from the start of its range
-    int32_t *cnt;       // [4 n_cells] in-tile prefix of blocks / values / dofs, diagonal rank | offset << 8
+    int32_t *cnt;       // [4 n_cells] prefix of blocks / values / dofs in the cell's tile, diagonal rank | offset << 8
     int64_t *tile_sum;  // [3 n_tiles]
     int64_t *tile_off;  // [3 (n_tiles + 1)] exclusive scan, totals last
     int32_t *err;       // set when a cell exceeds the preparation kernel's limits

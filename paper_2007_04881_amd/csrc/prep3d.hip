@@ -11,8 +11,9 @@
 //   ascending order (boundary faces last, one group per boundary code) by
 //   repeated wave minima over the neighbour ids, with each group's rank among
 //   the row's columns and the offset of its block inside the row;
-// * the row's counts (blocks, values, dofs), turned into in-tile prefixes
-//   and tile sums by a one-work-group scan.
+// * the row's counts (blocks, values, dofs) as prefixes inside the
+//   work-group's tile of 4 cells, and the tile sums, which a one-work-group
+//   kernel scans.
 #include "dgp3d.h"
 #include "kernels.h"
 
@@ -21,7 +22,8 @@ namespace dgp {
 namespace {
 
 constexpr int WG3 = 256;
-constexpr int CPW = WG3 / 64;             // cells per work-group
+constexpr int CPW = WG3 / 64;             // cells per work-group (one tile)
+static_assert(CPW == kPrepTile3D, "tile size");
 constexpr int FSL = kMaxFaces3D / 64;     // face slots per lane
 constexpr int HSL = kVtxHash3D / 64;      // hash slots per lane in the compaction
 constexpr int kBoundaryKey = 0x7fffff00;  // group key of boundary faces: this | boundary code
@@ -58,9 +60,12 @@ __device__ __forceinline__ double readlane_dbl(double v, int l) {
 __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3Out out) {
     __shared__ int s_hash[CPW][kVtxHash3D];
     __shared__ int s_list[CPW][kVtxHash3D];
+    __shared__ int s_cnt[CPW][3];
 
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    // the cell, its face count and its distinct-vertex count are wave-uniform:
+    // keep them in scalar registers so loops over them are uniform
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c = blockIdx.x * CPW + w;
     const bool valid = c < m.n_cells;
     int64_t fs = 0;
@@ -79,13 +84,14 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
     __syncthreads();
 
     // ---- faces: group keys, and their vertices into the hash set
+    const int nq = (nf + 63) / 64;  // face slots in use (uniform)
     int key[FSL], fid[FSL];
 #pragma unroll
     for (int q = 0; q < FSL; ++q) {
         const int k = lane + 64 * q;
         key[q] = INT_MAX;
         fid[q] = 0;
-        if (k < nf) {
+        if (q < nq && k < nf) {
             const int F = m.cell_face[fs + k];
             fid[q] = F;
             const int o = other_cell(m, F, c);
@@ -123,32 +129,38 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
         const int t = __shfl_up(incl, off, 64);
         if (lane >= off) incl += t;
     }
-    const int nu = __shfl(incl, 63, 64);
+    const int nu = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
     int pos = incl - nmine;
 #pragma unroll
     for (int k = 0; k < HSL; ++k)
         if (mine[k] >= 0) s_list[w][pos++] = mine[k];
     __syncthreads();
 
-    // ---- bounding box and diameter over the distinct vertices (FP64)
+    // ---- bounding box and diameter over the distinct vertices (FP64).  Lanes
+    // hold vertices lane, lane + 64, ...; empty slots repeat vertex 0, which
+    // changes neither the box nor the largest distance.
     constexpr int OWN = kVtxHash3D / 64;
+    const int nk = (nu + 63) / 64;  // uniform
     double ox[OWN], oy[OWN], oz[OWN];
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    {
+        const int v0 = nu > 0 ? s_list[w][0] : 0;
 #pragma unroll
-    for (int k = 0; k < OWN; ++k) {
-        const int i = lane + 64 * k;
-        ox[k] = oy[k] = oz[k] = 0.0;
-        if (i < nu) {
-            const int v = s_list[w][i];
-            ox[k] = m.x[v];
-            oy[k] = m.y[v];
-            oz[k] = m.z[v];
-            lo[0] = fmin(lo[0], ox[k]);
-            lo[1] = fmin(lo[1], oy[k]);
-            lo[2] = fmin(lo[2], oz[k]);
-            hi[0] = fmax(hi[0], ox[k]);
-            hi[1] = fmax(hi[1], oy[k]);
-            hi[2] = fmax(hi[2], oz[k]);
+        for (int k = 0; k < OWN; ++k) {
+            ox[k] = oy[k] = oz[k] = 0.0;
+            if (k < nk) {
+                const int i = lane + 64 * k;
+                const int v = i < nu ? s_list[w][i] : v0;
+                ox[k] = m.x[v];
+                oy[k] = m.y[v];
+                oz[k] = m.z[v];
+                lo[0] = fmin(lo[0], ox[k]);
+                lo[1] = fmin(lo[1], oy[k]);
+                lo[2] = fmin(lo[2], oz[k]);
+                hi[0] = fmax(hi[0], ox[k]);
+                hi[1] = fmax(hi[1], oy[k]);
+                hi[2] = fmax(hi[2], oz[k]);
+            }
         }
     }
     for (int d = 0; d < 3; ++d) {
@@ -158,7 +170,6 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
     // all pairs: vertex j of chunk k2 is broadcast from its lane, each lane
     // compares it with the vertices it holds
     double d2 = 0.0;
-    const int nk = (nu + 63) / 64;
 #pragma unroll
     for (int k2 = 0; k2 < OWN; ++k2) {
         if (k2 < nk) {
@@ -167,7 +178,7 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
                 const double xj = readlane_dbl(ox[k2], l), yj = readlane_dbl(oy[k2], l), zj = readlane_dbl(oz[k2], l);
 #pragma unroll
                 for (int k = 0; k < OWN; ++k) {
-                    if (k < nk && lane + 64 * k < nu) {
+                    if (k < nk) {
                         const double dx = ox[k] - xj, dy = oy[k] - yj, dz = oz[k] - zj;
                         d2 = fmax(d2, dx * dx + dy * dy + dz * dz);
                     }
@@ -186,16 +197,18 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
         int kmin = INT_MAX;
 #pragma unroll
         for (int q = 0; q < FSL; ++q)
-            if (key[q] > prev && key[q] < kmin) kmin = key[q];
+            if (q < nq && key[q] > prev && key[q] < kmin) kmin = key[q];
         kmin = wave_min_i(kmin);
         if (kmin == INT_MAX) break;
         int cg = 0;
 #pragma unroll
         for (int q = 0; q < FSL; ++q) {
-            const bool hit = key[q] == kmin;
-            const uint64_t bal = __ballot(hit);
-            if (hit) out.forder[fs + start + cg + __popcll(bal & lt)] = fid[q];
-            cg += __popcll(bal);
+            if (q < nq) {
+                const bool hit = key[q] == kmin;
+                const uint64_t bal = __ballot(hit);
+                if (hit) out.forder[fs + start + cg + __popcll(bal & lt)] = fid[q];
+                cg += __popcll(bal);
+            }
         }
         FaceGroup g;
         g.start = start;
@@ -241,39 +254,45 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
         g.n_groups = ng;
         g.pad[0] = g.pad[1] = g.pad[2] = 0;
         out.geo[c] = g;
-        out.cnt[4 * c + 0] = 1 + nbrs;
-        out.cnt[4 * c + 1] = nbc * (nbc + vsum);
-        out.cnt[4 * c + 2] = nbc;
-        out.cnt[4 * c + 3] = below | ((nbc * vbelow) << 8);
         if (err || nu >= (kVtxHash3D * 3) / 4) atomicOr(out.err, err ? err : 2);
+    }
+    // the row's counts; prefixes inside the work-group's tile of CPW cells
+    if (lane == 0) {
+        s_cnt[w][0] = valid ? 1 + nbrs : 0;
+        s_cnt[w][1] = valid ? nbc * (nbc + vsum) : 0;
+        s_cnt[w][2] = valid ? nbc : 0;
+    }
+    __syncthreads();
+    if (valid && lane == 0) {
+        int pb = 0, pv = 0, pd = 0;
+        for (int k = 0; k < w; ++k) {
+            pb += s_cnt[k][0];
+            pv += s_cnt[k][1];
+            pd += s_cnt[k][2];
+        }
+        out.cnt[4 * c + 0] = pb;
+        out.cnt[4 * c + 1] = pv;
+        out.cnt[4 * c + 2] = pd;
+        out.cnt[4 * c + 3] = below | ((nbc * vbelow) << 8);
+    }
+    if (threadIdx.x < 3) {
+        int64_t sum = 0;
+        for (int k = 0; k < CPW; ++k) sum += s_cnt[k][threadIdx.x];
+        out.tile_sum[3 * blockIdx.x + threadIdx.x] = sum;
     }
 }
 
-// Per-cell counts -> in-tile exclusive prefixes (in place) and tile sums, then
-// an exclusive scan of the tile sums with the totals after the last tile.  One
-// work-group; each thread owns a run of consecutive tiles.
-__global__ void __launch_bounds__(1024) k_scan3d(int n_cells, int32_t *__restrict__ cnt,
-                                                 int64_t *__restrict__ tile_sum, int64_t *__restrict__ tile_off) {
+// Exclusive scan of the tile sums (blocks, values, dofs) into tile_off, totals
+// after the last tile.  One work-group; each thread sums a run of tiles.
+__global__ void __launch_bounds__(1024) k_scan3d(int n_tiles, const int64_t *__restrict__ tile_sum,
+                                                 int64_t *__restrict__ tile_off) {
     __shared__ int64_t sh[3][1024];
-    const int n_tiles = (n_cells + kPrepTile - 1) / kPrepTile;
     const int t = threadIdx.x;
     const int per = (n_tiles + 1023) / 1024;
     const int a = t * per, b = min(a + per, n_tiles);
     int64_t run[3] = {0, 0, 0};
-    for (int i = a; i < b; ++i) {
-        int acc[3] = {0, 0, 0};
-        const int c1 = min(n_cells, (i + 1) * kPrepTile);
-        for (int c = i * kPrepTile; c < c1; ++c)
-            for (int q = 0; q < 3; ++q) {
-                const int v = cnt[4 * c + q];
-                cnt[4 * c + q] = acc[q];
-                acc[q] += v;
-            }
-        for (int q = 0; q < 3; ++q) {
-            tile_sum[3 * i + q] = acc[q];
-            run[q] += acc[q];
-        }
-    }
+    for (int i = a; i < b; ++i)
+        for (int q = 0; q < 3; ++q) run[q] += tile_sum[3 * i + q];
     for (int q = 0; q < 3; ++q) sh[q][t] = run[q];
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -296,8 +315,9 @@ __global__ void __launch_bounds__(1024) k_scan3d(int n_cells, int32_t *__restric
 }
 
 void launch_prep3d(const DevMesh &m, const DevProblem &pr, const Prep3Out &out, hipStream_t st) {
-    hipLaunchKernelGGL(k_prep3d, dim3((m.n_cells + CPW - 1) / CPW), dim3(WG3), 0, st, m, pr, out);
-    hipLaunchKernelGGL(k_scan3d, dim3(1), dim3(1024), 0, st, m.n_cells, out.cnt, out.tile_sum, out.tile_off);
+    const int n_tiles = (m.n_cells + kPrepTile3D - 1) / kPrepTile3D;
+    hipLaunchKernelGGL(k_prep3d, dim3(n_tiles), dim3(WG3), 0, st, m, pr, out);
+    hipLaunchKernelGGL(k_scan3d, dim3(1), dim3(1024), 0, st, n_tiles, out.tile_sum, out.tile_off);
 }
 
 }  // namespace dgp

@@ -333,7 +333,7 @@ static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     UP(face_opp, F, face_opp)
 #undef UP
     const int64_t nnzb_max = N + n_cf;
-    ctx->n_tiles = (int)((N + kPrepTile - 1) / kPrepTile);
+    ctx->n_tiles = (int)((N + kPrepTile3D - 1) / kPrepTile3D);
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t o_geo = 0;
     const size_t o_ord = o_geo + al(sizeof(CellGeo3) * (size_t)N);
