@@ -79,8 +79,9 @@ typedef struct dgp_ctx dgp_ctx;
  *   cell_face / cell_face_ptr in any order; face_opp names the vertex of the
  *   left cell's tetrahedron opposite the triangle (it fixes the outward
  *   normal); degrees 1..2 (the degree-4 tetrahedron and triangle rules);
- *   at most 1024 faces per cell.  dgp_pattern fails with DGP_EUNSUPPORTED if
- *   a cell's boundary has more than 768 distinct vertices. */
+ *   at most 1024 faces per cell, fewer than 2^27 faces.  dgp_pattern fails
+ *   with DGP_EUNSUPPORTED if a cell's boundary has more than 384 distinct
+ *   vertices. */
 typedef struct {
     int32_t dim;                  /* 2 or 3 */
     int64_t n_vertices;

@@ -113,11 +113,10 @@ __constant__ MomIdx<4> c_mom4 = kMom4;
 // packed upper-triangle index of (i <= j) in an n x n symmetric block
 __host__ __device__ constexpr int pk(int n, int i, int j) { return i * n - i * (i - 1) / 2 + (j - i); }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+// wavefront sum of the ROCm device library (DPP; declared by HIP's headers only
+// under HIP_ENABLE_EXTRA_WARP_SYNC_TYPES)
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_add_f64(double);
+__device__ __forceinline__ double wave_sum(double v) { return __ockl_wfred_add_f64(v); }
 
 // Manufactured data in 3D (constant a): u, grad u and f = -a lap u + b . grad u + c u
 struct Trig3 {
@@ -185,14 +184,13 @@ __device__ __forceinline__ void basis3(const T *xi, const T *nc, T *u, T *g) {
     }
 }
 
-// A point of the 6-point rule on face triangle gface[pi / 6]: position,
-// unit normal out of cell c, weight (rule weight x triangle area).
-struct FacePt {
-    double x[3], n[3], w;
+// A face triangle as seen from cell c: first vertex, edges, unit normal out of
+// c and area.  One lane computes it (one chain of dependent loads per face)
+// and stores it in LDS, where the six lanes of its points read it.
+struct FaceLds {
+    double p0[3], e1[3], e2[3], n[3], area;
 };
-__device__ __forceinline__ void face_point(const DevMesh &m, int c, const int32_t *gface, int pi, FacePt &fp) {
-    const int fk = pi / DGP_TRI4_N, q = pi - DGP_TRI4_N * fk;
-    const int F = gface[fk];
+__device__ __forceinline__ void face_stage(const DevMesh &m, int c, int F, FaceLds &f) {
     const int iv0 = m.face_vtx[3 * F], iv1 = m.face_vtx[3 * F + 1], iv2 = m.face_vtx[3 * F + 2];
     const int io = m.face_opp[F];
     const bool left = m.face_cell[2 * F] == c;
@@ -209,11 +207,29 @@ __device__ __forceinline__ void face_point(const DevMesh &m, int c, const int32_
     if (!left) sg = -sg;
     const double il = sg / len;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) fp.n[d] = cr[d] * il;
-    fp.w = c_tri4_w[q] * 0.5 * len;
-    const double l0 = c_tri4_l[3 * q], l1 = c_tri4_l[3 * q + 1], l2 = c_tri4_l[3 * q + 2];
+    for (int d = 0; d < 3; ++d) {
+        f.p0[d] = p0[d];
+        f.e1[d] = e1[d];
+        f.e2[d] = e2[d];
+        f.n[d] = cr[d] * il;
+    }
+    f.area = 0.5 * len;
+}
+
+// Point pi of the staged faces (6-point rule, face pi / 6): position, normal, weight.
+struct FacePt {
+    double x[3], n[3], w;
+};
+__device__ __forceinline__ void face_point(const FaceLds *fl, int pi, FacePt &fp) {
+    const int fk = pi / DGP_TRI4_N, q = pi - DGP_TRI4_N * fk;
+    const FaceLds &f = fl[fk];
+    const double l1 = c_tri4_l[3 * q + 1], l2 = c_tri4_l[3 * q + 2];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) fp.x[d] = l0 * p0[d] + l1 * p1[d] + l2 * p2[d];
+    for (int d = 0; d < 3; ++d) {
+        fp.x[d] = f.p0[d] + l1 * f.e1[d] + l2 * f.e2[d];
+        fp.n[d] = f.n[d];
+    }
+    fp.w = c_tri4_w[q] * f.area;
 }
 
 // The row's box, offsets and face groups (all wave-uniform).
@@ -396,6 +412,7 @@ __global__ void __launch_bounds__(256, 2) k_vol3d(Asm3Args A) {
 // to what the element kernel wrote.
 template <typename T, int P>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Args A) {
+    __shared__ FaceLds s_face[4][64];
     constexpr int NB = nb3d(P), NBN = nb3d(kMaxP3D);
     constexpr int NPK = NB * (NB + 1) / 2;  // packed symmetric entries
     constexpr int NXE = NB * NBN;           // cross-block entries (neighbour basis up to degree 2)
@@ -405,12 +422,14 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
     const DevMesh &m = A.m;
     const DevProblem &pr = A.pr;
     const int lane = threadIdx.x & 63;
-    const int wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wid = blockIdx.x * 4 + wv;
     if (wid >= A.n_rows) return;
     const int c = A.rows ? __builtin_amdgcn_readfirstlane(A.rows[wid]) : wid;
     Row3 R;
     row_begin(A, c, R);
     const CellGeo3 &G = A.geo[c];
+    FaceLds *sf = s_face[wv];
     const double *cx = R.cx, *ctr = R.ctr;
     const double isq = R.isq;
     const int64_t fs = R.fs, pre_b = R.pre_b, pre_v = R.pre_v, pre_d = R.pre_d;
@@ -452,7 +471,6 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
         const FaceGroup gr = A.grp[fs + gi];
         const int code = gr.code;
         if (code < 0) continue;
-        const int npts = DGP_TRI4_N * gr.count;
         const int32_t *gface = A.forder + fs + gr.start;
         const CellGeo3 &Gn = A.geo[code];
         const int pn = m.cell_p[code];
@@ -470,9 +488,13 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
         for (int k = 0; k < NX0; ++k) xa0[k] = T(0);
 #pragma unroll
         for (int k = 0; k < NX1; ++k) xa1[k] = T(0);
-        for (int pi = lane; pi < npts; pi += 64) {
+        for (int f0 = 0; f0 < gr.count; f0 += 64) {
+        const int nfc = min(64, gr.count - f0);
+        if (lane < nfc) face_stage(m, c, gface[f0 + lane], sf[lane]);
+        wave_sync();
+        for (int pi = lane; pi < DGP_TRI4_N * nfc; pi += 64) {
             FacePt fp;
-            face_point(m, c, gface, pi, fp);
+            face_point(sf, pi, fp);
             const double bn = pr.bx * fp.n[0] + pr.by * fp.n[1] + pr.bz * fp.n[2];
             const T tha = T(-fp.w * 0.5 * a), ths = T(fp.w * (pen - (bn < 0.0 ? bn : 0.0)));
             T xi[3], nc[3], u[NB], g[NB], v[NBN], gv[NBN];
@@ -506,6 +528,8 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
                 }
             }
         }
+        wave_sync();
+        }
         // entry e = i * NBN + j of the degree-2 neighbour basis; the neighbour's
         // first nbo functions are its basis of degree p_n
         WaveRS<T, 32, NX0>::run(xa0, lane);
@@ -533,7 +557,6 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
         const FaceGroup gr = A.grp[fs + gi];
         const int code = gr.code;
         const bool inner = code >= 0;
-        const int npts = DGP_TRI4_N * gr.count;
         const int32_t *gface = A.forder + fs + gr.start;
         const double theta = inner ? 0.5 : 1.0;
         double pen = pr.c_sigma * pen_r;
@@ -542,9 +565,13 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
             const int pn = m.cell_p[code];
             pen = uniform(pr.c_sigma * fmax(pen_r, Gn.abar * (pn * pn) / Gn.h));
         }
-        for (int pi = lane; pi < npts; pi += 64) {
+        for (int f0 = 0; f0 < gr.count; f0 += 64) {
+        const int nfc = min(64, gr.count - f0);
+        if (lane < nfc) face_stage(m, c, gface[f0 + lane], sf[lane]);
+        wave_sync();
+        for (int pi = lane; pi < DGP_TRI4_N * nfc; pi += 64) {
             FacePt fp;
-            face_point(m, c, gface, pi, fp);
+            face_point(sf, pi, fp);
             const double bn = pr.bx * fp.n[0] + pr.by * fp.n[1] + pr.bz * fp.n[2];
             const double ha = -fp.w * theta * a, hs = fp.w * (pen - (bn < 0.0 ? bn : 0.0));
             T xi[3], nc[3], u[NB], g[NB];
@@ -586,6 +613,8 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
                     for (int i = 0; i < NB; ++i) rf[i] = fma(u[i], gn, rf[i]);
                 }
             }
+        }
+        wave_sync();
         }
     }
     WaveRS<T, 32, NPK>::run(dp, lane);

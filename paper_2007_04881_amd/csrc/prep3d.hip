@@ -16,6 +16,7 @@
 //   kernel scans.
 #include "dgp3d.h"
 #include "kernels.h"
+#include "wave.h"
 
 namespace dgp {
 
@@ -24,30 +25,19 @@ namespace {
 constexpr int WG3 = 256;
 constexpr int CPW = WG3 / 64;             // cells per work-group (one tile)
 static_assert(CPW == kPrepTile3D, "tile size");
-constexpr int FSL = kMaxFaces3D / 64;     // face slots per lane
 constexpr int HSL = kVtxHash3D / 64;      // hash slots per lane in the compaction
+constexpr int OWN = kMaxVtx3D / 64;       // distinct vertices per lane
 constexpr int kBoundaryKey = 0x7fffff00;  // group key of boundary faces: this | boundary code
 
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_min_d(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_max_d(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
+// wavefront reductions of the ROCm device library (declared by HIP's headers
+// only under HIP_ENABLE_EXTRA_WARP_SYNC_TYPES for the 64-bit types)
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_min_f64(double);
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_max_f64(double);
+
+__device__ __forceinline__ int wave_min_i(int v) { return __ockl_wfred_min_i32(v); }
+__device__ __forceinline__ int wave_max_i(int v) { return __ockl_wfred_max_i32(v); }
+__device__ __forceinline__ double wave_min_d(double v) { return __ockl_wfred_min_f64(v); }
+__device__ __forceinline__ double wave_max_d(double v) { return __ockl_wfred_max_f64(v); }
 __device__ __forceinline__ double readlane_dbl(double v, int l) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
@@ -58,8 +48,10 @@ __device__ __forceinline__ double readlane_dbl(double v, int l) {
 }  // namespace
 
 __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3Out out) {
-    __shared__ int s_hash[CPW][kVtxHash3D];
-    __shared__ int s_list[CPW][kVtxHash3D];
+    // per wave: the hash set of distinct vertices, then (reused) the face keys;
+    // the compacted vertex list, then (reused) the face ids with the neighbour sizes
+    __shared__ int s_a[CPW][kVtxHash3D];
+    __shared__ int s_b[CPW][kVtxHash3D];
     __shared__ int s_cnt[CPW][3];
 
     const int lane = threadIdx.x & 63;
@@ -80,49 +72,33 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
         err = 1;
         nf = 0;
     }
-    for (int k = lane; k < kVtxHash3D; k += 64) s_hash[w][k] = -1;
+    int *hash = s_a[w], *list = s_b[w];
+    for (int k = lane; k < kVtxHash3D; k += 64) hash[k] = -1;
     __syncthreads();
 
-    // ---- faces: group keys, and their vertices into the hash set
-    const int nq = (nf + 63) / 64;  // face slots in use (uniform)
-    int key[FSL], fid[FSL];
-#pragma unroll
-    for (int q = 0; q < FSL; ++q) {
-        const int k = lane + 64 * q;
-        key[q] = INT_MAX;
-        fid[q] = 0;
-        if (q < nq && k < nf) {
-            const int F = m.cell_face[fs + k];
-            fid[q] = F;
-            const int o = other_cell(m, F, c);
-            key[q] = o >= 0 ? o : (kBoundaryKey | (int)m.face_bc[F]);
-            for (int t = 0; t < 3; ++t) {
-                const int v = m.face_vtx[3 * F + t];
-                int slot = (int)(((unsigned)v * 2654435761u) >> 22) & (kVtxHash3D - 1);
-                bool placed = false;
-                for (int probe = 0; probe < kVtxHash3D; ++probe) {
-                    const int old = atomicCAS(&s_hash[w][slot], -1, v);
-                    if (old == -1 || old == v) {
-                        placed = true;
-                        break;
-                    }
-                    slot = (slot + 1) & (kVtxHash3D - 1);
+    // ---- the vertices of the cell's faces into the hash set
+    for (int k = lane; k < nf; k += 64) {
+        const int F = m.cell_face[fs + k];
+        for (int t = 0; t < 3; ++t) {
+            const int v = m.face_vtx[3 * F + t];
+            int slot = (int)(((unsigned)v * 2654435761u) >> 22) & (kVtxHash3D - 1);
+            bool placed = false;
+            for (int probe = 0; probe < kVtxHash3D; ++probe) {
+                const int old = atomicCAS(&hash[slot], -1, v);
+                if (old == -1 || old == v) {
+                    placed = true;
+                    break;
                 }
-                if (!placed) err = 2;
+                slot = (slot + 1) & (kVtxHash3D - 1);
             }
+            if (!placed) err = 2;
         }
     }
     __syncthreads();
 
-    // ---- compact the distinct vertices into s_list[w][0 .. nu)
-    int mine[HSL];
+    // ---- compact the distinct vertices into list[0 .. nu)
     int nmine = 0;
-#pragma unroll
-    for (int k = 0; k < HSL; ++k) {
-        const int v = s_hash[w][lane * HSL + k];
-        mine[k] = v;
-        nmine += v >= 0;
-    }
+    for (int k = 0; k < HSL; ++k) nmine += hash[lane * HSL + k] >= 0;
     int incl = nmine;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -131,26 +107,27 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
     }
     const int nu = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
     int pos = incl - nmine;
-#pragma unroll
-    for (int k = 0; k < HSL; ++k)
-        if (mine[k] >= 0) s_list[w][pos++] = mine[k];
+    for (int k = 0; k < HSL; ++k) {
+        const int v = hash[lane * HSL + k];
+        if (v >= 0) list[pos++] = v;
+    }
+    if (nu > 64 * OWN) err = 3;
     __syncthreads();
 
     // ---- bounding box and diameter over the distinct vertices (FP64).  Lanes
     // hold vertices lane, lane + 64, ...; empty slots repeat vertex 0, which
     // changes neither the box nor the largest distance.
-    constexpr int OWN = kVtxHash3D / 64;
-    const int nk = (nu + 63) / 64;  // uniform
+    const int nk = min((nu + 63) / 64, OWN);  // uniform
     double ox[OWN], oy[OWN], oz[OWN];
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     {
-        const int v0 = nu > 0 ? s_list[w][0] : 0;
+        const int v0 = nu > 0 ? list[0] : 0;
 #pragma unroll
         for (int k = 0; k < OWN; ++k) {
             ox[k] = oy[k] = oz[k] = 0.0;
             if (k < nk) {
                 const int i = lane + 64 * k;
-                const int v = i < nu ? s_list[w][i] : v0;
+                const int v = i < nu ? list[i] : v0;
                 ox[k] = m.x[v];
                 oy[k] = m.y[v];
                 oz[k] = m.z[v];
@@ -167,55 +144,112 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
         lo[d] = wave_min_d(lo[d]);
         hi[d] = wave_max_d(hi[d]);
     }
-    // all pairs: vertex j of chunk k2 is broadcast from its lane, each lane
-    // compares it with the vertices it holds
+    // Diameter.  With c the box centre and R the largest |v - c|, a pair can
+    // only be longer than a known pair (length L) if both ends satisfy
+    // |v - c| >= L - R (|v_i - v_j| <= |v_i - c| + |v_j - c|).  L starts as the
+    // distance from the vertex farthest from c to the vertex farthest from it;
+    // only the vertices passing the test are then compared with all others, so
+    // the longest pair, whose ends both pass, is among the compared ones.
+    const double cc[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+    double r2[OWN];
+    double r2max = 0.0;
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+        r2[k] = 0.0;
+        if (k < nk) {
+            const double dx = ox[k] - cc[0], dy = oy[k] - cc[1], dz = oz[k] - cc[2];
+            r2[k] = dx * dx + dy * dy + dz * dz;
+            r2max = fmax(r2max, r2[k]);
+        }
+    }
+    r2max = wave_max_d(r2max);
+    double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+    for (int k = OWN - 1; k >= 0; --k) {
+        if (k < nk) {
+            const uint64_t hit = __ballot(r2[k] == r2max);
+            if (hit) {
+                const int l = __builtin_ctzll(hit);
+                ax = readlane_dbl(ox[k], l);
+                ay = readlane_dbl(oy[k], l);
+                az = readlane_dbl(oz[k], l);
+            }
+        }
+    }
     double d2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+        if (k < nk) {
+            const double dx = ox[k] - ax, dy = oy[k] - ay, dz = oz[k] - az;
+            d2 = fmax(d2, dx * dx + dy * dy + dz * dz);
+        }
+    }
+    d2 = wave_max_d(d2);
+    // candidates: |v - c| >= L - R, with a relative margin for rounding
+    const double thr = sqrt(d2) - sqrt(r2max);
+    const double thr2 = thr > 0.0 ? thr * thr * (1.0 - 1e-9) : 0.0;
+    double d2c = d2;
 #pragma unroll
     for (int k2 = 0; k2 < OWN; ++k2) {
         if (k2 < nk) {
-            const int cnt = min(64, nu - 64 * k2);
-            for (int l = 0; l < cnt; ++l) {
+            uint64_t cand = __ballot(r2[k2] >= thr2);
+            while (cand) {
+                const int l = __builtin_ctzll(cand);
+                cand &= cand - 1;
                 const double xj = readlane_dbl(ox[k2], l), yj = readlane_dbl(oy[k2], l), zj = readlane_dbl(oz[k2], l);
 #pragma unroll
                 for (int k = 0; k < OWN; ++k) {
                     if (k < nk) {
                         const double dx = ox[k] - xj, dy = oy[k] - yj, dz = oz[k] - zj;
-                        d2 = fmax(d2, dx * dx + dy * dy + dz * dz);
+                        d2c = fmax(d2c, dx * dx + dy * dy + dz * dz);
                     }
                 }
             }
         }
     }
-    d2 = wave_max_d(d2);
+    d2 = wave_max_d(d2c);
     err = wave_max_i(err);
+    __syncthreads();  // the hash set and the vertex list are free from here on
 
-    // ---- face groups: neighbours ascending, then boundary codes
+    // ---- face groups: neighbours ascending, then boundary codes.  Keys in
+    // hash[], face ids with the neighbour's basis size (bits 27..30) in list[].
+    int *key = hash, *fid = list;
+    for (int k = lane; k < nf; k += 64) {
+        const int F = m.cell_face[fs + k];
+        const int o = other_cell(m, F, c);
+        key[k] = o >= 0 ? o : (kBoundaryKey | (int)m.face_bc[F]);
+        fid[k] = F | ((o >= 0 ? nb3d(m.cell_p[o]) : 0) << 27);
+    }
+    wave_sync();
     const int nbc = nb3d(p);
     int prev = -1, start = 0, ng = 0, nbrs = 0, vsum = 0, below = 0, vbelow = 0;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     while (true) {
         int kmin = INT_MAX;
-#pragma unroll
-        for (int q = 0; q < FSL; ++q)
-            if (q < nq && key[q] > prev && key[q] < kmin) kmin = key[q];
+        for (int k = lane; k < nf; k += 64) {
+            const int kk = key[k];
+            if (kk > prev && kk < kmin) kmin = kk;
+        }
         kmin = wave_min_i(kmin);
         if (kmin == INT_MAX) break;
-        int cg = 0;
-#pragma unroll
-        for (int q = 0; q < FSL; ++q) {
-            if (q < nq) {
-                const bool hit = key[q] == kmin;
-                const uint64_t bal = __ballot(hit);
-                if (hit) out.forder[fs + start + cg + __popcll(bal & lt)] = fid[q];
-                cg += __popcll(bal);
+        int cg = 0, nbo = 0;
+        for (int k0 = 0; k0 < nf; k0 += 64) {
+            const int k = k0 + lane;
+            const bool hit = k < nf && key[k] == kmin;
+            const uint64_t bal = __ballot(hit);
+            if (hit) {
+                const int f = fid[k];
+                out.forder[fs + start + cg + __popcll(bal & lt)] = f & 0x07ffffff;
+                nbo = f >> 27;
             }
+            cg += __popcll(bal);
         }
         FaceGroup g;
         g.start = start;
         g.count = cg;
         if (kmin < kBoundaryKey) {
             const int o = kmin;
-            const int nbo = nb3d(m.cell_p[o]);
+            nbo = wave_max_i(nbo);
             const int rank = nbrs + (o > c ? 1 : 0);
             const int voff = nbc * vsum + (o > c ? nbc * nbc : 0);
             g.code = o;
@@ -254,7 +288,7 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
         g.n_groups = ng;
         g.pad[0] = g.pad[1] = g.pad[2] = 0;
         out.geo[c] = g;
-        if (err || nu >= (kVtxHash3D * 3) / 4) atomicOr(out.err, err ? err : 2);
+        if (err) atomicOr(out.err, err);
     }
     // the row's counts; prefixes inside the work-group's tile of CPW cells
     if (lane == 0) {

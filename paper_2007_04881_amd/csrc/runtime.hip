@@ -252,8 +252,8 @@ static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     if (m->n_cells <= 0 || m->n_vertices <= 0 || m->n_faces <= 0)
         return fail(ctx, DGP_EINVAL, "empty mesh (cells %lld, vertices %lld, faces %lld)", (long long)m->n_cells,
                     (long long)m->n_vertices, (long long)m->n_faces);
-    if (m->n_cells > INT32_MAX / 2 || m->n_faces > INT32_MAX / 2 || m->n_vertices > INT32_MAX / 2)
-        return fail(ctx, DGP_EUNSUPPORTED, "mesh too large for 32-bit ids");
+    if (m->n_cells > INT32_MAX / 2 || m->n_faces >= (int64_t(1) << 27) || m->n_vertices > INT32_MAX / 2)
+        return fail(ctx, DGP_EUNSUPPORTED, "mesh too large (3D: fewer than 2^27 faces)");
     if (!m->x || !m->y || !m->z || !m->cell_ptr || !m->cell_vtx || !m->cell_p || !m->cell_face_ptr ||
         !m->cell_face || !m->face_vtx || !m->face_cell || !m->face_bc || !m->face_opp)
         return fail(ctx, DGP_EINVAL, "null mesh array");
@@ -410,8 +410,9 @@ dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
         HIPCHK(ctx, hipMemcpyAsync(&err3, ctx->prep3.err, sizeof(err3), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (err3)
-        return fail(ctx, DGP_EUNSUPPORTED, "a polyhedron exceeds the preparation kernel's limits (%d faces, %d distinct surface vertices)",
-                    kMaxFaces3D, (kVtxHash3D * 3) / 4);
+        return fail(ctx, DGP_EUNSUPPORTED,
+                    "a polyhedron exceeds the preparation kernel's limits (%d faces, %d distinct surface vertices)",
+                    kMaxFaces3D, kMaxVtx3D);
     ctx->nnzb = tot[0];
     ctx->n_vals = tot[1];
     ctx->n_dofs = tot[2];
