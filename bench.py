@@ -301,7 +301,7 @@ def main():
         "kernel_ms": avg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_row2d<float,2,2,true>", "algorithmic_bytes": abytes},
+                     "kernel": "k_row2d<float,2,2,false,true>", "algorithmic_bytes": abytes},
     }
     ctx.close()
     if not args.no_reduced:
