@@ -29,6 +29,7 @@
 // cross block is written after its group; the face part of the diagonal block
 // and of the load after the last group, added to the element part.  The basis
 // normalisation s_i s'_j is applied to the finished sums in FP64.
+#include <type_traits>
 #include <utility>
 
 #include "dgp3d.h"
@@ -416,8 +417,9 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
     constexpr int NB = nb3d(P), NBN = nb3d(kMaxP3D);
     constexpr int NPK = NB * (NB + 1) / 2;  // packed symmetric entries
     constexpr int NXE = NB * NBN;           // cross-block entries (neighbour basis up to degree 2)
-    constexpr int NX0 = NXE < 64 ? NXE : 64, NX1 = NXE - NX0;
-    static_assert(NPK <= 64 && NB * NB <= 128 && NX1 <= 64, "one or two entries per lane");
+    constexpr int NCH = (NXE + 31) / 32;    // cross-block chunks of 32 entries (one per half-wave lane)
+    static_assert(NCH <= 4, "at most four chunks");
+    static_assert(NPK <= 64 && NB * NB <= 128, "one or two entries per lane");
 
     const DevMesh &m = A.m;
     const DevProblem &pr = A.pr;
@@ -467,85 +469,100 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
     const double a = pr.a0;
     const double pen_r = uniform(G.abar * (P * P) / G.h);
     T *vals = static_cast<T *>(A.vals);
-    for (int gi = 0; gi < ng; ++gi) {
-        const FaceGroup gr = A.grp[fs + gi];
-        const int code = gr.code;
-        if (code < 0) continue;
-        const int32_t *gface = A.forder + fs + gr.start;
-        const CellGeo3 &Gn = A.geo[code];
-        const int pn = m.cell_p[code];
+    // Sweep A: two interior groups at a time, one per half-wave (lanes 0-31 and
+    // 32-63), so the reduce-scatter of a cross block runs over 32 lanes and two
+    // blocks share each reduction step.  Interior groups come first in a row's
+    // group list (neighbours ascending), boundary groups last.
+    int n_in = 0;
+    while (n_in < ng && A.grp[fs + n_in].code >= 0) ++n_in;
+    const int h = lane >> 5, hl = lane & 31;
+    FaceLds *sfh = sf + 32 * h;
+    for (int gp = 0; gp < n_in; gp += 2) {
+        const int gi = gp + h;
+        const bool gvalid = gi < n_in;
+        FaceGroup gr;
+        gr.start = gr.count = gr.rank_voff = 0;
+        gr.code = c;
+        if (gvalid) gr = A.grp[fs + gi];
+        const CellGeo3 &Gn = A.geo[gr.code];
+        const int pn = m.cell_p[gr.code];
         const int nbo = nb3d(pn);
         double ncx[3], nctr[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            ncx[d] = uniform(2.0 / (Gn.hi[d] - Gn.lo[d]));
-            nctr[d] = uniform(0.5 * (Gn.lo[d] + Gn.hi[d]));
+            ncx[d] = 2.0 / (Gn.hi[d] - Gn.lo[d]);
+            nctr[d] = 0.5 * (Gn.lo[d] + Gn.hi[d]);
         }
-        const double nisq = uniform(1.0 / Gn.sqrt_box);
-        const double pen = uniform(pr.c_sigma * fmax(pen_r, Gn.abar * (pn * pn) / Gn.h));
-        T xa0[64], xa1[64];
+        const double nisq = 1.0 / Gn.sqrt_box;
+        const double pen = pr.c_sigma * fmax(pen_r, Gn.abar * (pn * pn) / Gn.h);
+        const int cnt = gr.count;
+        const int cmax = max(__builtin_amdgcn_readlane(cnt, 0), __builtin_amdgcn_readlane(cnt, 32));
+        T xa[NCH][64];
 #pragma unroll
-        for (int k = 0; k < NX0; ++k) xa0[k] = T(0);
+        for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-        for (int k = 0; k < NX1; ++k) xa1[k] = T(0);
-        for (int f0 = 0; f0 < gr.count; f0 += 64) {
-        const int nfc = min(64, gr.count - f0);
-        if (lane < nfc) face_stage(m, c, gface[f0 + lane], sf[lane]);
-        wave_sync();
-        for (int pi = lane; pi < DGP_TRI4_N * nfc; pi += 64) {
-            FacePt fp;
-            face_point(sf, pi, fp);
-            const double bn = pr.bx * fp.n[0] + pr.by * fp.n[1] + pr.bz * fp.n[2];
-            const T tha = T(-fp.w * 0.5 * a), ths = T(fp.w * (pen - (bn < 0.0 ? bn : 0.0)));
-            T xi[3], nc[3], u[NB], g[NB], v[NBN], gv[NBN];
+            for (int k = 0; k < 32; ++k) xa[ch][k] = T(0);
+        for (int f0 = 0; f0 < cmax; f0 += 32) {
+            const int nfc = min(32, cnt - f0);
+            if (hl < nfc) face_stage(m, c, A.forder[fs + gr.start + f0 + hl], sfh[hl]);
+            wave_sync();
+            for (int pi = hl; pi < DGP_TRI4_N * nfc; pi += 32) {
+                FacePt fp;
+                face_point(sfh, pi, fp);
+                const double bn = pr.bx * fp.n[0] + pr.by * fp.n[1] + pr.bz * fp.n[2];
+                const T tha = T(-fp.w * 0.5 * a), ths = T(fp.w * (pen - (bn < 0.0 ? bn : 0.0)));
+                T xi[3], nc[3], u[NB], g[NB], v[NBN], gv[NBN];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                xi[d] = T((fp.x[d] - ctr[d]) * cx[d]);
-                nc[d] = T(fp.n[d] * cx[d]);
-            }
-            basis3<T, NB>(xi, nc, u, g);
+                for (int d = 0; d < 3; ++d) {
+                    xi[d] = T((fp.x[d] - ctr[d]) * cx[d]);
+                    nc[d] = T(fp.n[d] * cx[d]);
+                }
+                basis3<T, NB>(xi, nc, u, g);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                xi[d] = T((fp.x[d] - nctr[d]) * ncx[d]);
-                nc[d] = T(fp.n[d] * ncx[d]);
-            }
-            basis3<T, NBN>(xi, nc, v, gv);
-            // X_ij += u_i (ha g'_j - hs v_j) + g_i (-ha v_j)   (u_0 = 1, g_0 = 0)
+                for (int d = 0; d < 3; ++d) {
+                    xi[d] = T((fp.x[d] - nctr[d]) * ncx[d]);
+                    nc[d] = T(fp.n[d] * ncx[d]);
+                }
+                basis3<T, NBN>(xi, nc, v, gv);
+                // X_ij += u_i (ha g'_j - hs v_j) + g_i (-ha v_j)   (u_0 = 1, g_0 = 0)
 #pragma unroll
-            for (int j = 0; j < NBN; ++j) {
-                const T tx = tha * gv[j] - ths * v[j];
-                const T ux = -tha * v[j];
+                for (int j = 0; j < NBN; ++j) {
+                    const T tx = tha * gv[j] - ths * v[j];
+                    const T ux = -tha * v[j];
 #pragma unroll
-                for (int i = 0; i < NB; ++i) {
-                    const int e = i * NBN + j;
-                    T &acc = e < 64 ? xa0[e < 64 ? e : 0] : xa1[e >= 64 ? e - 64 : 0];
-                    if (i == 0) {
-                        acc += tx;
-                    } else {
-                        acc = fma(u[i], tx, acc);
-                        acc = fma(g[i], ux, acc);
+                    for (int i = 0; i < NB; ++i) {
+                        const int e = i * NBN + j;
+                        T &acc = xa[e / 32][e % 32];
+                        if (i == 0) {
+                            acc += tx;
+                        } else {
+                            acc = fma(u[i], tx, acc);
+                            acc = fma(g[i], ux, acc);
+                        }
                     }
                 }
             }
+            wave_sync();
         }
-        wave_sync();
-        }
-        // entry e = i * NBN + j of the degree-2 neighbour basis; the neighbour's
-        // first nbo functions are its basis of degree p_n
-        WaveRS<T, 32, NX0>::run(xa0, lane);
-        if (NX1 > 0) WaveRS<T, 32, (NX1 > 0 ? NX1 : 1)>::run(xa1, lane);
-        const int64_t base = pre_v + (gr.rank_voff >> 8);
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int e = lane + 64 * r;
-            if (e < NXE) {
-                const int i = e / NBN, j = e % NBN;
-                if (j < nbo) {
-                    const double sum = double(r == 0 ? xa0[0] : xa1[0]);
-                    vals[base + i * nbo + j] = T(sum * (c_norm3[i] * isq) * (c_norm3[j] * nisq));
+        // entry e = 32 ch + (lane & 31) of the degree-2 neighbour basis; the
+        // neighbour's first nbo functions are its basis of degree p_n
+        auto reduce_write = [&](auto chc) {
+            constexpr int ch = decltype(chc)::value;
+            if constexpr (ch < NCH) {
+                WaveRS<T, 16, (NXE - 32 * ch < 32 ? NXE - 32 * ch : 32)>::run(xa[ch], lane);
+                const int e = 32 * ch + hl;
+                if (gvalid && e < NXE) {
+                    const int i = e / NBN, j = e % NBN;
+                    if (j < nbo)
+                        vals[pre_v + (gr.rank_voff >> 8) + i * nbo + j] =
+                            T(double(xa[ch][0]) * (c_norm3[i] * isq) * (c_norm3[j] * nisq));
                 }
             }
-        }
+        };
+        reduce_write(std::integral_constant<int, 0>{});
+        reduce_write(std::integral_constant<int, 1>{});
+        reduce_write(std::integral_constant<int, 2>{});
+        reduce_write(std::integral_constant<int, 3>{});
     }
 
     T dp[64], rf[64];

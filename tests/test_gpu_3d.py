@@ -74,6 +74,57 @@ def test_neumann_faces(precision):
     _case(m, DAR3, precision)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_cells_and_groups(precision):
+    """Three polyhedra of about 1,000 tetrahedra each: several hundred faces per
+    cell and interfaces of more than 64 triangles (staged in several chunks)."""
+    m = agglomerated_cube(8, 3, 2029, p=2)
+    fc = m.face_cell.reshape(-1, 2)
+    inner = fc[fc[:, 1] >= 0]
+    _, counts = np.unique(inner, axis=0, return_counts=True)
+    assert counts.max() > 64
+    _case(m, DAR3, precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_unordered_face_lists(precision):
+    """Each cell's face list in a random order: the preparation kernel groups the
+    faces by neighbour itself (the pattern is unchanged, the sums are reordered)."""
+    m = agglomerated_cube(8, 70, 2030, p=2)
+    rng = np.random.default_rng(3)
+    cf = m.cell_face.copy()
+    for c in range(m.n_cells):
+        s, e = m.cell_face_ptr[c], m.cell_face_ptr[c + 1]
+        cf[s:e] = rng.permutation(cf[s:e])
+    m.cell_face = cf
+    _case(m, DAR3, precision)
+
+
+def test_3d_graph_replay_deterministic():
+    """The captured whole path replayed: every replay bit-identical to the eager result."""
+    import torch
+    import paper_2007_04881_amd as D
+
+    m = agglomerated_cube(8, 70, 2031, p=2)
+    ctx = D.Context(0)
+    ctx.upload(m)
+    ctx.pattern()
+    vals, rhs = ctx.outputs(1)
+    ctx.run(DAR3, 1, vals, rhs)
+    torch.cuda.synchronize()
+    v0, r0 = vals.clone(), rhs.clone()
+    ctx.graph_capture(0, DAR3, 1, vals, rhs)
+    for _ in range(4):
+        vals.fill_(float("nan"))
+        rhs.fill_(float("nan"))
+        ctx.graph_launch()
+        torch.cuda.synchronize()
+        assert torch.equal(vals, v0) and torch.equal(rhs, r0)
+        ctx.run(DAR3, 1, vals, rhs)  # eager work between replays
+        torch.cuda.synchronize()
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision", [1, 0])
 def test_workload4_full_size_sampled(precision):
     """128^3 cubes, 12.6M Kuhn tetrahedra in 32,768 polyhedra, p = 2: full
