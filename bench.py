@@ -154,6 +154,31 @@ def reduced_rule_study(D, torch, steps, warmup, train_polygons, train_epochs):
             "break_even_assemblies": (rulegen / gain) if gain > 0 else None}
 
 
+def mixed_degree_study(D, torch, steps, warmup):
+    """262,144-cell Voronoi mesh with degrees drawn from {1, 2, 3, 4} (Poisson):
+    whole-path graph replays and per-launch kernel times, FP32 and FP64."""
+    from meshgen import config_mesh, problem_params
+    log("mixed degrees: 262,144-cell mesh, p in 1..4")
+    mesh = config_mesh(3)
+    params = problem_params(3)
+    ctx = D.Context(0)
+    ctx.upload(mesh)
+    info = ctx.pattern()
+    out = {"workload": "2D Poisson, 262144-cell seeded Voronoi, p drawn from {1,2,3,4}",
+           "cells": mesh.n_cells, "nnzb": info.nnzb, "n_vals": info.n_vals, "n_dofs": info.n_dofs}
+    for prec, name in ((D.F32, "f32"), (D.F64, "f64")):
+        vals, rhs = ctx.outputs(prec)
+        ctx.graph_capture(0, params, prec, vals, rhs)
+        ms = _replay_ms(ctx, D, torch, steps, warmup)
+        ctx.run(params, prec, vals, rhs)
+        prep_ms, asm_ms = ctx.time_kernels(10)
+        out[name] = {"ms_per_step": ms, "block_nnz_per_s": info.nnzb / (ms * 1e-3),
+                     "kernel_ms": {"prep": prep_ms, "assemble": asm_ms}}
+        del vals, rhs
+    ctx.close()
+    return out
+
+
 def polyhedra_study(D, torch, steps, warmup):
     """3D Poisson (A = I) on the 128^3-cube Kuhn mesh agglomerated into 32,768
     polyhedra (about 384 tetrahedra each), p = 2 (10 dofs per cell): the whole
@@ -213,6 +238,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-rule study")
     ap.add_argument("--no-3d", action="store_true", help="skip the polyhedral (3D) workload")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree 262,144-cell workload")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for HBM counter runs: 10 whole steps of the headline workload, then 10 copies of a "
                          "64 MiB tensor (the copy calibrates FETCH_SIZE / WRITE_SIZE); prints no JSON")
@@ -306,6 +332,8 @@ def main():
     ctx.close()
     if not args.no_reduced:
         out["reduced_rules"] = reduced_rule_study(D, torch, 20, 3, args.train_polygons, args.train_epochs)
+    if not args.no_mixed:
+        out["mixed_degrees"] = mixed_degree_study(D, torch, 20, 3)
     if not args.no_3d:
         out["polyhedra"] = polyhedra_study(D, torch, 20, 3)
     if not args.no_cpu:

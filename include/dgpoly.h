@@ -81,7 +81,7 @@ typedef struct dgp_ctx dgp_ctx;
  *   normal); degrees 1..2 (the degree-4 tetrahedron and triangle rules);
  *   at most 1024 faces per cell, fewer than 2^27 faces.  dgp_pattern fails
  *   with DGP_EUNSUPPORTED if a cell's boundary has more than 384 distinct
- *   vertices. */
+ *   vertices or the cell has more than 64 neighbours and boundary codes. */
 typedef struct {
     int32_t dim;                  /* 2 or 3 */
     int64_t n_vertices;

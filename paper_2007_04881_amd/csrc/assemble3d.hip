@@ -190,6 +190,8 @@ __device__ __forceinline__ void basis3(const T *xi, const T *nc, T *u, T *g) {
 // and stores it in LDS, where the six lanes of its points read it.
 struct FaceLds {
     double p0[3], e1[3], e2[3], n[3], area;
+    double pen, theta;  // the face group's penalty and consistency factor (diagonal sweep)
+    int code;           // neighbour id, or -1 Dirichlet, -2 Neumann (diagonal sweep)
 };
 __device__ __forceinline__ void face_stage(const DevMesh &m, int c, int F, FaceLds &f) {
     const int iv0 = m.face_vtx[3 * F], iv1 = m.face_vtx[3 * F + 1], iv2 = m.face_vtx[3 * F + 2];
@@ -216,6 +218,15 @@ __device__ __forceinline__ void face_stage(const DevMesh &m, int c, int F, FaceL
     }
     f.area = 0.5 * len;
 }
+
+// A face group of the row with what its points need: the neighbour's box
+// factors, the penalty, the range in the grouped face list.  Filled once per
+// row, one lane per group, so the sweeps read it from LDS instead of chains
+// of dependent loads.
+struct GroupLds {
+    double ncx[3], nctr[3], nisq, pen;
+    int start, count, code, rank_voff, nbo, pad;
+};
 
 // Point pi of the staged faces (6-point rule, face pi / 6): position, normal, weight.
 struct FacePt {
@@ -414,6 +425,7 @@ __global__ void __launch_bounds__(256, 2) k_vol3d(Asm3Args A) {
 template <typename T, int P>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Args A) {
     __shared__ FaceLds s_face[4][64];
+    __shared__ GroupLds s_group[4][kMaxGroups3D];
     constexpr int NB = nb3d(P), NBN = nb3d(kMaxP3D);
     constexpr int NPK = NB * (NB + 1) / 2;  // packed symmetric entries
     constexpr int NXE = NB * NBN;           // cross-block entries (neighbour basis up to degree 2)
@@ -469,6 +481,38 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
     const double a = pr.a0;
     const double pen_r = uniform(G.abar * (P * P) / G.h);
     T *vals = static_cast<T *>(A.vals);
+    GroupLds *sg = s_group[wv];
+    for (int gi = lane; gi < ng; gi += 64) {
+        const FaceGroup gr = A.grp[fs + gi];
+        GroupLds e;
+        e.start = gr.start;
+        e.count = gr.count;
+        e.code = gr.code;
+        e.rank_voff = gr.rank_voff;
+        e.pad = 0;
+        e.pen = pr.c_sigma * pen_r;
+        e.nbo = 0;
+        e.nisq = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            e.ncx[d] = 1.0;
+            e.nctr[d] = 0.0;
+        }
+        if (gr.code >= 0) {
+            const CellGeo3 &Gn = A.geo[gr.code];
+            const int pn = m.cell_p[gr.code];
+            e.nbo = nb3d(pn);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                e.ncx[d] = 2.0 / (Gn.hi[d] - Gn.lo[d]);
+                e.nctr[d] = 0.5 * (Gn.lo[d] + Gn.hi[d]);
+            }
+            e.nisq = 1.0 / Gn.sqrt_box;
+            e.pen = pr.c_sigma * fmax(pen_r, Gn.abar * (pn * pn) / Gn.h);
+        }
+        sg[gi] = e;
+    }
+    wave_sync();
     // Sweep A: two interior groups at a time, one per half-wave (lanes 0-31 and
     // 32-63), so the reduce-scatter of a cross block runs over 32 lanes and two
     // blocks share each reduction step.  Interior groups come first in a row's
@@ -480,22 +524,18 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
     for (int gp = 0; gp < n_in; gp += 2) {
         const int gi = gp + h;
         const bool gvalid = gi < n_in;
-        FaceGroup gr;
-        gr.start = gr.count = gr.rank_voff = 0;
-        gr.code = c;
-        if (gvalid) gr = A.grp[fs + gi];
-        const CellGeo3 &Gn = A.geo[gr.code];
-        const int pn = m.cell_p[gr.code];
-        const int nbo = nb3d(pn);
+        const GroupLds &gg = sg[gvalid ? gi : gp];
+        const int nbo = gg.nbo;
         double ncx[3], nctr[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            ncx[d] = 2.0 / (Gn.hi[d] - Gn.lo[d]);
-            nctr[d] = 0.5 * (Gn.lo[d] + Gn.hi[d]);
+            ncx[d] = gg.ncx[d];
+            nctr[d] = gg.nctr[d];
         }
-        const double nisq = 1.0 / Gn.sqrt_box;
-        const double pen = pr.c_sigma * fmax(pen_r, Gn.abar * (pn * pn) / Gn.h);
-        const int cnt = gr.count;
+        const double nisq = gg.nisq;
+        const double pen = gg.pen;
+        const int gstart = gg.start, grank_voff = gg.rank_voff;
+        const int cnt = gvalid ? gg.count : 0;
         const int cmax = max(__builtin_amdgcn_readlane(cnt, 0), __builtin_amdgcn_readlane(cnt, 32));
         T xa[NCH][64];
 #pragma unroll
@@ -504,7 +544,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
             for (int k = 0; k < 32; ++k) xa[ch][k] = T(0);
         for (int f0 = 0; f0 < cmax; f0 += 32) {
             const int nfc = min(32, cnt - f0);
-            if (hl < nfc) face_stage(m, c, A.forder[fs + gr.start + f0 + hl], sfh[hl]);
+            if (hl < nfc) face_stage(m, c, A.forder[fs + gstart + f0 + hl], sfh[hl]);
             wave_sync();
             for (int pi = hl; pi < DGP_TRI4_N * nfc; pi += 32) {
                 FacePt fp;
@@ -554,7 +594,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
                 if (gvalid && e < NXE) {
                     const int i = e / NBN, j = e % NBN;
                     if (j < nbo)
-                        vals[pre_v + (gr.rank_voff >> 8) + i * nbo + j] =
+                        vals[pre_v + (grank_voff >> 8) + i * nbo + j] =
                             T(double(xa[ch][0]) * (c_norm3[i] * isq) * (c_norm3[j] * nisq));
                 }
             }
@@ -565,32 +605,34 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
         reduce_write(std::integral_constant<int, 3>{});
     }
 
+    // Sweep B: the face part of the diagonal block and of the load, over the
+    // row's faces in chunks of 64 regardless of group boundaries (each staged
+    // face carries its group's penalty, weight factor and boundary code).
     T dp[64], rf[64];
 #pragma unroll
     for (int k = 0; k < NPK; ++k) dp[k] = T(0);
 #pragma unroll
     for (int k = 0; k < NB; ++k) rf[k] = T(0);
-    for (int gi = 0; gi < ng; ++gi) {
-        const FaceGroup gr = A.grp[fs + gi];
-        const int code = gr.code;
-        const bool inner = code >= 0;
-        const int32_t *gface = A.forder + fs + gr.start;
-        const double theta = inner ? 0.5 : 1.0;
-        double pen = pr.c_sigma * pen_r;
-        if (inner) {
-            const CellGeo3 &Gn = A.geo[code];
-            const int pn = m.cell_p[code];
-            pen = uniform(pr.c_sigma * fmax(pen_r, Gn.abar * (pn * pn) / Gn.h));
+    const int nfr = (int)(m.cell_face_ptr[c + 1] - fs);
+    for (int f0 = 0; f0 < nfr; f0 += 64) {
+        const int nfc = min(64, nfr - f0);
+        const int k = f0 + lane;
+        if (lane < nfc) {
+            int gi = 0;  // the group holding face k (groups are consecutive ranges)
+            while (gi + 1 < ng && sg[gi + 1].start <= k) ++gi;
+            face_stage(m, c, A.forder[fs + k], sf[lane]);
+            sf[lane].pen = sg[gi].pen;
+            sf[lane].theta = sg[gi].code >= 0 ? 0.5 : 1.0;
+            sf[lane].code = sg[gi].code;
         }
-        for (int f0 = 0; f0 < gr.count; f0 += 64) {
-        const int nfc = min(64, gr.count - f0);
-        if (lane < nfc) face_stage(m, c, gface[f0 + lane], sf[lane]);
         wave_sync();
         for (int pi = lane; pi < DGP_TRI4_N * nfc; pi += 64) {
             FacePt fp;
             face_point(sf, pi, fp);
+            const FaceLds &fl = sf[pi / DGP_TRI4_N];
+            const int code = fl.code;
             const double bn = pr.bx * fp.n[0] + pr.by * fp.n[1] + pr.bz * fp.n[2];
-            const double ha = -fp.w * theta * a, hs = fp.w * (pen - (bn < 0.0 ? bn : 0.0));
+            const double ha = -fp.w * fl.theta * a, hs = fp.w * (fl.pen - (bn < 0.0 ? bn : 0.0));
             T xi[3], nc[3], u[NB], g[NB];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -617,7 +659,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
                     }
                 }
             }
-            if (!inner) {
+            if (code < 0) {
                 double ue, gu[3];
                 exact3(pr, tc, fp.x, &ue, gu, nullptr);
                 if (code == -1) {
@@ -632,7 +674,6 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
             }
         }
         wave_sync();
-        }
     }
     WaveRS<T, 32, NPK>::run(dp, lane);
     WaveRS<T, 32, NB>::run(rf, lane);

@@ -19,6 +19,7 @@ constexpr int kMaxP3D = 2;         // 3D kernels are built for p = 1, 2
 constexpr int kMaxFaces3D = 1024;  // boundary triangles of one polyhedron handled by the preparation kernel
 constexpr int kVtxHash3D = 1024;   // LDS hash slots per polyhedron for its distinct surface vertices
 constexpr int kMaxVtx3D = 384;     // distinct surface vertices of one polyhedron handled by the preparation kernel
+constexpr int kMaxGroups3D = 64;  // face groups (neighbours and boundary codes) of one polyhedron
 constexpr int kPrepTile3D = 4;     // cells per tile of the 3D row offsets (one preparation work-group)
 
 __host__ __device__ constexpr int nb3d(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }

@@ -266,6 +266,7 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
         }
         if (lane == 0) out.grp[fs + ng] = g;
         ng += 1;
+        if (ng > kMaxGroups3D) err = 4;
         start += cg;
         prev = kmin;
     }
@@ -288,7 +289,7 @@ __global__ void __launch_bounds__(WG3) k_prep3d(DevMesh m, DevProblem pr, Prep3O
         g.n_groups = ng;
         g.pad[0] = g.pad[1] = g.pad[2] = 0;
         out.geo[c] = g;
-        if (err) atomicOr(out.err, err);
+        if (err) atomicOr(out.err, err);  // 1 faces, 2 or 3 distinct vertices, 4 face groups
     }
     // the row's counts; prefixes inside the work-group's tile of CPW cells
     if (lane == 0) {

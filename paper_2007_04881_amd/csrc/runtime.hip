@@ -411,8 +411,9 @@ dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (err3)
         return fail(ctx, DGP_EUNSUPPORTED,
-                    "a polyhedron exceeds the preparation kernel's limits (%d faces, %d distinct surface vertices)",
-                    kMaxFaces3D, kMaxVtx3D);
+                    "a polyhedron exceeds the 3D kernels' limits (%d faces, %d distinct surface vertices, "
+                    "%d neighbours and boundary codes)",
+                    kMaxFaces3D, kMaxVtx3D, kMaxGroups3D);
     ctx->nnzb = tot[0];
     ctx->n_vals = tot[1];
     ctx->n_dofs = tot[2];
