@@ -182,6 +182,18 @@ dgp_status dgp_kernel_ms(dgp_ctx *ctx, const char *name, float *ms);
  * must still be allocated).  Synchronous. */
 dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assemble_ms);
 
+/* Launch tuning per degree bin (the rows grouped by degree, Section 3.1's
+ * grouping of elements by p).  For the last dgp_run / dgp_assemble on a 2D
+ * mesh with plain rules, times each degree bin's row kernel in its two
+ * register budgets (the default, and one more wave per SIMD) within about
+ * budget_ms milliseconds of device time and keeps the faster for later
+ * launches of that precision and degree.  Values of the last call's output
+ * buffers are rewritten (they must still be allocated).  3D meshes and
+ * reduced rules have a single configuration (nothing changes).  choice: NULL
+ * or int32[2][5], the variant in use per [FP64, FP32][degree 0..4] on return.
+ * Synchronous.  DGP_EINVAL if budget_ms < 1, DGP_ESTATE before an assembly. */
+dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice);
+
 /* ---------------------------------------------------------------------
  * Reduced volume rules for polygons (an extension of Section 3: the paper
  * integrates on the fan sub-triangles only).  Every element with at most 12

@@ -68,7 +68,7 @@ class TrainStats(C.Structure):
 
 EXPORTS = ["dgp_create", "dgp_destroy", "dgp_set_stream", "dgp_last_error", "dgp_mesh_upload", "dgp_pattern",
            "dgp_pattern_copy", "dgp_assemble", "dgp_run", "dgp_graph_capture", "dgp_graph_launch",
-           "dgp_set_timing", "dgp_kernel_ms", "dgp_time_kernels", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
+           "dgp_set_timing", "dgp_kernel_ms", "dgp_time_kernels", "dgp_autotune", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
            "dgp_qrule_cell_data", "dgp_train_polygons", "dgp_mlp_forward", "dgp_mlp_loss_grad", "dgp_adam_step",
            "dgp_mlp_train"]
 
@@ -113,6 +113,7 @@ def lib():
         L.dgp_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.dgp_kernel_ms.argtypes = [C.c_void_p, C.c_char_p, C.POINTER(C.c_float)]
         L.dgp_time_kernels.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.dgp_autotune.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         _lib = L
     return _lib
 
@@ -252,6 +253,13 @@ class Context:
         a, b = C.c_float(), C.c_float()
         self._check(lib().dgp_time_kernels(self._h, reps, C.byref(a), C.byref(b)), "dgp_time_kernels")
         return a.value, b.value
+
+    def autotune(self, budget_ms=200):
+        """Pick each degree bin's row-kernel register budget for the last
+        assembly's precision; returns the [FP64, FP32][degree] choice table."""
+        out = (C.c_int32 * 10)()
+        self._check(lib().dgp_autotune(self._h, int(budget_ms), C.cast(out, C.c_void_p)), "dgp_autotune")
+        return [[out[q * 5 + p] for p in range(5)] for q in range(2)]
 
     def kernel_ms(self, name: str) -> float:
         ms = C.c_float()

@@ -345,8 +345,10 @@ __device__ __forceinline__ void row_slices(const AsmArgs &A, const RowCtx &R, st
 }  // namespace
 
 // MX: neighbours may have other degrees than P (up to PN); otherwise all have degree P = PN
-template <typename T, int P, int PN, bool MX, bool ADV>
-__global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW)) k_row2d(AsmArgs A) {
+// ALT = 1 asks the register allocator for one more wave per SIMD than the
+// measured default (dgp_autotune picks between the two per degree and precision)
+template <typename T, int P, int PN, bool MX, bool ADV, int ALT>
+__global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(AsmArgs A) {
     using C = RowCfg<T, P, PN>;
     constexpr int NB = C::NB, FG = C::FG;
     const DevMesh &m = A.m;
@@ -469,23 +471,30 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW)) k_row2d(AsmArgs
 }
 
 template <typename T, int P, int PN, bool MX>
-static void launch_row(const AsmArgs &a, hipStream_t st) {
+static void launch_row(const AsmArgs &a, int alt, hipStream_t st) {
     const bool adv = a.pr.bx != 0.0 || a.pr.by != 0.0 || a.pr.c != 0.0;
     const int nb = (a.n_rows + 3) / 4;
     if (nb <= 0) return;
-    if (adv)
-        hipLaunchKernelGGL((k_row2d<T, P, PN, MX, true>), dim3(nb), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_row2d<T, P, PN, MX, false>), dim3(nb), dim3(256), 0, st, a);
+    if (adv) {
+        if (alt)
+            hipLaunchKernelGGL((k_row2d<T, P, PN, MX, true, 1>), dim3(nb), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_row2d<T, P, PN, MX, true, 0>), dim3(nb), dim3(256), 0, st, a);
+    } else {
+        if (alt)
+            hipLaunchKernelGGL((k_row2d<T, P, PN, MX, false, 1>), dim3(nb), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_row2d<T, P, PN, MX, false, 0>), dim3(nb), dim3(256), 0, st, a);
+    }
 }
 
-bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, hipStream_t st) {
+bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, int alt, hipStream_t st) {
 #define DGP_ROW(T, PP)                                      \
     if (p == PP) {                                          \
         if (mixed)                                          \
-            launch_row<T, PP, kMaxP, true>(a, st);          \
+            launch_row<T, PP, kMaxP, true>(a, alt, st);     \
         else                                                \
-            launch_row<T, PP, PP, false>(a, st);            \
+            launch_row<T, PP, PP, false>(a, alt, st);       \
         return true;                                        \
     }
     if (precision == 0) {

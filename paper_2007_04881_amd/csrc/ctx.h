@@ -65,6 +65,9 @@ struct dgp_ctx {
     int last_precision = 0, last_rule = 0;
     void *last_vals = nullptr, *last_rhs = nullptr;
 
+    // register-budget variant of the 2D row kernel per [precision][degree] (dgp_autotune)
+    int8_t row_alt[2][dgp::kMaxP + 1] = {};
+
     bool timing = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool ev_pattern = false, ev_assemble = false;

@@ -15,7 +15,8 @@ void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hip
 // One wave per element row: pattern (if a.write_pattern) and values of rows
 // a.rows[0 .. n_rows) (all rows in order if a.rows is null), all of degree p;
 // mixed: neighbours may have any degree up to kMaxP (else all have degree p).
-bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, hipStream_t st);
+// alt: 0 = the default register budget, 1 = one more wave per SIMD (see dgp_autotune)
+bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, int alt, hipStream_t st);
 
 // ---- polyhedral (3D) meshes
 // Geometry, face groups and row counts of every cell, then the tile scan.

@@ -538,8 +538,9 @@ static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precis
     a.qr_nodes = ctx->qr_nodes;
     a.qr_w = ctx->qr_w;
     a.qr_ok = ctx->qr_ok;
+    const int pi = precision == DGP_F32 ? 1 : 0;
     if (ctx->p_uniform > 0) {
-        if (!launch_row2d(a, precision, ctx->p_uniform, false, st))
+        if (!launch_row2d(a, precision, ctx->p_uniform, false, ctx->row_alt[pi][ctx->p_uniform], st))
             return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, ctx->p_uniform);
     } else {
         for (int p = 1; p <= kMaxP; ++p) {
@@ -547,7 +548,7 @@ static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precis
             if (n == 0) continue;
             a.rows = ctx->rows_by_p + ctx->rows_off[p];
             a.n_rows = (int32_t)n;
-            if (!launch_row2d(a, precision, p, true, st))
+            if (!launch_row2d(a, precision, p, true, ctx->row_alt[pi][p], st))
                 return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
         }
     }
@@ -658,6 +659,79 @@ dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assem
     if (prep_ms) *prep_ms = a / reps;
     if (assemble_ms) *assemble_ms = b / reps;
     ctx->ev_pattern = ctx->ev_assemble = false;
+    return DGP_OK;
+}
+
+dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice) {
+    if (!ctx || budget_ms < 1) return DGP_EINVAL;
+    if (!ctx->has_last) return fail(ctx, DGP_ESTATE, "dgp_autotune before an assembly (it tunes the last one)");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (ctx->dim == 2 && ctx->last_rule == DGP_RULE_PLAIN) {
+        hipStream_t st = ctx->stream;
+        const int pi = ctx->last_precision == DGP_F32 ? 1 : 0;
+        AsmArgs a;
+        a.m = ctx->dm;
+        a.pr = ctx->last_pr;
+        a.geo = ctx->prep.geo;
+        a.nbr = ctx->prep.nbr;
+        a.cnt = ctx->prep.cnt;
+        a.tile_off = ctx->prep.tile_off;
+        a.erec = ctx->prep.erec;
+        a.row_ptr = ctx->row_ptr;
+        a.col_idx = ctx->col_idx;
+        a.val_ptr = ctx->val_ptr;
+        a.dof_ptr = ctx->dof_ptr;
+        a.vals = ctx->last_vals;
+        a.rhs = ctx->last_rhs;
+        a.values = 1;
+        a.write_pattern = 0;
+        a.reduced = 0;
+        a.qr_nodes = ctx->qr_nodes;
+        a.qr_w = ctx->qr_w;
+        a.qr_ok = ctx->qr_ok;
+        int bins[kMaxP + 1] = {}, nbins = 0;
+        for (int p = 1; p <= kMaxP; ++p) {
+            const bool present = ctx->p_uniform > 0 ? p == ctx->p_uniform : ctx->rows_off[p + 1] > ctx->rows_off[p];
+            if (present) bins[nbins++] = p;
+        }
+        // each variant of each bin gets an equal share of the budget (at least one launch)
+        const float share = (float)budget_ms / (float)(2 * (nbins > 0 ? nbins : 1));
+        for (int b = 0; b < nbins; ++b) {
+            const int p = bins[b];
+            const bool mixed = ctx->p_uniform <= 0;
+            a.rows = mixed ? ctx->rows_by_p + ctx->rows_off[p] : nullptr;
+            a.n_rows = (int32_t)(mixed ? ctx->rows_off[p + 1] - ctx->rows_off[p] : ctx->n_cells);
+            float best = 0.0f;
+            int best_alt = 0;
+            for (int alt = 0; alt < 2; ++alt) {
+                // one warm launch, then as many timed launches as fit in the share
+                HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
+                launch_row2d(a, ctx->last_precision, p, mixed, alt, st);
+                HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
+                HIPCHK(ctx, hipEventSynchronize(ctx->ev[1]));
+                float one = 0.0f;
+                HIPCHK(ctx, hipEventElapsedTime(&one, ctx->ev[0], ctx->ev[1]));
+                const int reps = one > 0.0f ? (int)fminf(50.0f, fmaxf(1.0f, share / one)) : 1;
+                HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
+                for (int r = 0; r < reps; ++r) launch_row2d(a, ctx->last_precision, p, mixed, alt, st);
+                HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
+                HIPCHK(ctx, hipGetLastError());
+                HIPCHK(ctx, hipEventSynchronize(ctx->ev[1]));
+                float ms = 0.0f;
+                HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+                ms /= (float)reps;
+                if (alt == 0 || ms < best) {
+                    best = ms;
+                    best_alt = alt;
+                }
+            }
+            ctx->row_alt[pi][p] = (int8_t)best_alt;
+        }
+        ctx->ev_pattern = ctx->ev_assemble = false;
+    }
+    if (choice)
+        for (int q = 0; q < 2; ++q)
+            for (int p = 0; p <= kMaxP; ++p) choice[q * (kMaxP + 1) + p] = ctx->row_alt[q][p];
     return DGP_OK;
 }
 

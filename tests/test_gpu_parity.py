@@ -172,3 +172,32 @@ def test_error_paths():
     with pytest.raises(ValueError):
         ctx.assemble(DAR, D.F64, v, r)
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotune_keeps_results(precision):
+    """dgp_autotune picks each degree bin's register budget; the arithmetic is
+    the same in both, so the values after tuning are bit-identical."""
+    import torch
+    import paper_2007_04881_amd as D
+
+    m = voronoi_mesh(1000, 83, lloyd=1, p=1)
+    m = m.with_degrees(np.random.default_rng(8).integers(1, 5, m.n_cells))
+    ctx = D.Context(0)
+    ctx.upload(m)
+    ctx.pattern()
+    vals, rhs = ctx.outputs(precision)
+    with pytest.raises(D.DgpError) as e:
+        ctx.autotune(50)
+    assert e.value.status == -6
+    ctx.assemble(DAR, precision, vals, rhs)
+    torch.cuda.synchronize()
+    v0, r0 = vals.clone(), rhs.clone()
+    choice = ctx.autotune(50)
+    assert all(c in (0, 1) for row in choice for c in row)
+    vals.fill_(float("nan"))
+    rhs.fill_(float("nan"))
+    ctx.assemble(DAR, precision, vals, rhs)
+    torch.cuda.synchronize()
+    assert torch.equal(vals, v0) and torch.equal(rhs, r0)
+    ctx.close()
