@@ -26,8 +26,8 @@ Mesh layout (all numpy arrays, host memory):
 """
 
 from .mesh import Mesh
-from .voronoi import voronoi_mesh, cartesian_mesh
+from .voronoi import voronoi_mesh, cartesian_mesh, split_cartesian_mesh
 from .kuhn import agglomerated_cube, cube_cells
 from .configs import config_mesh, problem_params, CONFIG_SEED_BASE
 
-__all__ = ["Mesh", "voronoi_mesh", "cartesian_mesh", "agglomerated_cube", "cube_cells", "config_mesh", "problem_params", "CONFIG_SEED_BASE"]
+__all__ = ["Mesh", "voronoi_mesh", "cartesian_mesh", "split_cartesian_mesh", "agglomerated_cube", "cube_cells", "config_mesh", "problem_params", "CONFIG_SEED_BASE"]

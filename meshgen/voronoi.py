@@ -200,3 +200,17 @@ def cartesian_mesh(nx: int, ny: int, p=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0) -> Mes
                for j in range(ny) for i in range(nx)]
     mesh = _build_mesh(verts, regions, f"cartesian({nx}x{ny})")
     return mesh.with_degrees(p)
+
+
+def split_cartesian_mesh(nx: int, ny: int, p=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0) -> Mesh:
+    """Rectangular nx x ny grid whose cell sides are all split at their midpoints:
+    every cell is an octagon with collinear vertices, and two neighbouring cells
+    share two edges (the mesh a refined neighbour leaves behind)."""
+    xs = np.linspace(x0, x1, 2 * nx + 1)
+    ys = np.linspace(y0, y1, 2 * ny + 1)
+    verts = np.array([[xs[i], ys[j]] for j in range(2 * ny + 1) for i in range(2 * nx + 1)])
+    vid = lambda i, j: j * (2 * nx + 1) + i
+    ring = [(0, 0), (1, 0), (2, 0), (2, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    regions = [[vid(2 * i + a, 2 * j + b) for a, b in ring] for j in range(ny) for i in range(nx)]
+    mesh = _build_mesh(verts, regions, f"split-cartesian({nx}x{ny})")
+    return mesh.with_degrees(p)

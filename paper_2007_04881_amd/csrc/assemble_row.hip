@@ -67,7 +67,13 @@ struct RowCfg {
     // waves per SIMD the register allocation must allow (measured: three waves
     // beat two for the FP32 p <= 2 kernels even with a small spill)
     static constexpr int MINW = (sizeof(T) == 4 && P <= 2 && PN <= 2) ? 3 : 1;
+    // cross blocks through a per-wave LDS table (XL) instead of per-column group sums
+    static constexpr bool XL = sizeof(T) == 4 && P <= 2 && PN <= 2;
+    static constexpr int XW = 3 * (NB + NBN);  // table row per lane: test terms, then trial terms
 };
+
+// sqrt(2a + 1): the normalisation of the one-dimensional Legendre factor of degree a
+constexpr double kSqrt2a1[kMaxP + 1] = {1.0, 1.7320508075688772, 2.23606797749979, 2.6457513110645907, 3.0};
 
 
 // Per-point coefficients of the rank-3 updates (see the file comment).
@@ -88,6 +94,8 @@ struct PointCoef {
 struct RowCtx {
     int lane, c, nv, vid, o, voff, dvoff, maxdup, QM, QF0, Qtot, QR;
     int gtab;  // lane g < number of groups: loop index of the g-th group's leading edge
+    int ng;    // number of edge groups
+    void *xs;  // the wave's cross-block table in LDS (XL kernels)
     bool red;
     uint64_t gmask;
     double ex, ey, x0, y0, isq, hx, hy, pen_r;  // x0, y0: the fan apex (first vertex)
@@ -95,6 +103,79 @@ struct RowCtx {
     Box bx;
     TrigCentre tc;
 };
+
+// Cross blocks of the edge groups in one pass of 64 points, through LDS.  Every
+// lane stores its point's normalised test terms u_a(i) (a = 0, 1, 2: d/dxi,
+// d/deta, value) and trial terms s_a(j) of the neighbour's normalised basis,
+// already scaled by the neighbour's box factor (zero for lanes without an
+// interior edge point).  Then each lane takes entries (group, i, j) of the
+// pass and sums u(i) . s(j) over the group's points: no cross-lane reductions,
+// and the entries of a block go out in row-major order.
+template <typename T, int P, int PN>
+__device__ __forceinline__ void cross_lds(const AsmArgs &A, const RowCtx &R, const Eval<T, P> &ev,
+                                          const PointCoef<T> &pc, double xin, double etan, double xsc, int base,
+                                          int d, int og, int gvoff, int fk) {
+    using C = RowCfg<T, P, PN>;
+    constexpr int NB = C::NB, NBN = C::NBN, XW = C::XW, FG = C::FG, NBX = NB * NBN;
+    constexpr int NGP = C::NG;  // Gauss points per edge (all neighbours have degree P here)
+    T *xs = static_cast<T *>(R.xs);
+    {
+        T Lx[PN + 1], dLx[PN + 1], Ly[PN + 1], dLy[PN + 1];
+        legendre<T, PN>(T(xin), Lx, dLx);
+        legendre<T, PN>(T(etan), Ly, dLy);
+#pragma unroll
+        for (int a = 1; a <= PN; ++a) {
+            Lx[a] *= T(kSqrt2a1[a]);
+            dLx[a] *= T(kSqrt2a1[a]);
+            Ly[a] *= T(kSqrt2a1[a]);
+            dLy[a] *= T(kSqrt2a1[a]);
+        }
+        const T xs_ = T(xsc);
+        const T sb0 = -pc.b0 * xs_, sb1 = -pc.b1 * xs_, sx0 = pc.x0 * xs_, sx1 = pc.x1 * xs_, sc2 = -pc.c2 * xs_;
+        T *row = xs + R.lane * XW;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            row[3 * i] = ev.g0[i] * T(kNorm[i]);
+            row[3 * i + 1] = ev.g1[i] * T(kNorm[i]);
+            row[3 * i + 2] = ev.v[i] * T(kNorm[i]);
+        }
+#pragma unroll
+        for (int j = 0; j < NBN; ++j) {
+            const T vj = Lx[exp_a(j)] * Ly[exp_b(j)];
+            const T gj0 = dLx[exp_a(j)] * Ly[exp_b(j)], gj1 = Lx[exp_a(j)] * dLy[exp_b(j)];
+            row[3 * NB + 3 * j] = sb0 * vj;
+            row[3 * NB + 3 * j + 1] = sb1 * vj;
+            row[3 * NB + 3 * j + 2] = fmat(sx0, gj0, fmat(sx1, gj1, sc2 * vj));
+        }
+    }
+    wave_sync();
+    // groups whose lanes lie in this pass (groups never straddle passes: 64 % FG == 0)
+    const int gfirst = base > R.QF0 ? (base - R.QF0) / FG : 0;
+    const int glast = min(R.ng, (base + 64 - R.QF0) / FG);
+    const int nent = (glast - gfirst) * NBX;
+    T *__restrict__ vals = static_cast<T *>(A.vals);
+    for (int e0 = 0; e0 < nent; e0 += 64) {
+        const int e = min(e0 + R.lane, nent - 1);
+        const int gl = e / NBX, r = e - gl * NBX, i = r / NBN, j = r - i * NBN;
+        const int ql = R.QF0 + (gfirst + gl) * FG - base;  // the group's first lane
+        const int oge = __shfl(og, ql, 64), gvo = __shfl(gvoff, ql, 64), fke = __shfl(fk, ql, 64);
+        const T *uu = xs + ql * XW + 3 * i;
+        const T *ss = xs + ql * XW + 3 * NB + 3 * j;
+        T sum = T(0);
+#pragma unroll
+        for (int p = 0; p < NGP; ++p)
+            sum = fmat(uu[p * XW], ss[p * XW],
+                       fmat(uu[p * XW + 1], ss[p * XW + 1], fmat(uu[p * XW + 2], ss[p * XW + 2], sum)));
+        if (e0 + R.lane < nent && oge >= 0 && fke >= 0) {
+            T *dst = vals + R.pre_v + gvo + i * NBN + j;
+            if (d == 0)
+                *dst = sum;
+            else
+                *dst += sum;
+        }
+    }
+    wave_sync();  // the table is rewritten by the next point set
+}
 
 template <typename T, int P, int PN, bool MX, bool ADV, int SL>
 __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
@@ -261,7 +342,9 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                 for (int i = 0; i < NB; ++i)
                     acc[ED + i] = fmat(ev.g0[i], pc.r0, fmat(ev.g1[i], pc.r1, fmat(ev.v[i], pc.r2, acc[ED + i])));
             }
-            if (pass_has_edges) {
+            if constexpr (C::XL) {
+                if (pass_has_edges) cross_lds<T, P, PN>(A, R, ev, pc, xin, etan, xsc, base, d, og, gvoff, fk);
+            } else if (pass_has_edges) {
                 // cross block, one column at a time: the group's lanes sum the column
                 // (butterfly inside the group) and lane gq writes the entries i = gq mod FG
                 T Lx[PN + 1], dLx[PN + 1], Ly[PN + 1], dLy[PN + 1];
@@ -447,6 +530,9 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     R.voff = voff;
     R.dvoff = dvoff;
     R.maxdup = max(dupc, 1);
+    R.ng = ng;
+    __shared__ T xlds[C::XL ? 4 * 64 * C::XW : 1];
+    R.xs = C::XL ? xlds + (threadIdx.x >> 6) * 64 * C::XW : nullptr;
     R.gmask = gmask;
     {
         // lane g gets the position of the g-th set bit of gmask

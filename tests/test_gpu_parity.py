@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from meshgen import cartesian_mesh, config_mesh, problem_params, voronoi_mesh
+from meshgen import cartesian_mesh, config_mesh, problem_params, split_cartesian_mesh, voronoi_mesh
 from tests.parity import TOL, block_errors, check_pattern, gpu_assemble, oracle_problem
 
 pytestmark = pytest.mark.gpu
@@ -103,6 +103,19 @@ def test_cartesian_and_neumann():
     left = np.isin(fv[:, 0], xl) & np.isin(fv[:, 1], xl)
     m2.face_bc[left] = 2
     _case(m2, DAR, 0)
+
+
+@pytest.mark.parametrize("p", [1, 2, "mixed"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_neighbours_sharing_two_edges(p, precision):
+    # octagons whose neighbours share two collinear edges each: the second edge
+    # of every neighbour group is a second point set added to the same block;
+    # 24 x 20 cells span several work-groups and a ragged last one
+    m = split_cartesian_mesh(24, 20, p=1 if p == "mixed" else p, x0=0.1, x1=1.3, y0=-0.2, y1=0.9)
+    if p == "mixed":
+        m = m.with_degrees(np.random.default_rng(5).integers(1, 4, m.n_cells))
+    _case(m, DAR, precision)
+    _case(m, POLY, precision)
 
 
 def test_single_cell_and_tiny():

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from meshgen import voronoi_mesh
+from meshgen import cartesian_mesh, split_cartesian_mesh, voronoi_mesh
 from tests import polyexact as PE
 
 
@@ -191,3 +191,22 @@ def test_manufactured_load_matches_the_pde():
         assert abs(f - f_fd) < 1e-5 * max(1.0, abs(f))
     for x, y in ((0.0, 0.37), (1.0, 0.81), (0.42, 0.0), (0.77, 1.0), (1.0, 1.0)):
         assert oracle.exact(prob, 2, np.array([x, y]))[0] == 0.0
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_split_edges_change_nothing(p):
+    """Splitting every side of a rectangular grid at its midpoint (octagons with
+    collinear vertices; neighbours share two edges, some fan triangles are
+    degenerate) describes the same cells and faces: with polynomial data every
+    integral is exact on each half, so the pattern and the matrix are those of
+    the plain grid."""
+    prob = oracle.Problem(a0=1.3, a1=0.0, b=(0.4, -0.7, 0.0), c=0.9, u_kind=oracle.U_POLY, u_poly=U_POLY)
+    plain = cartesian_mesh(4, 3, p=p, x0=0.1, x1=1.3, y0=-0.2, y1=0.9)
+    split = split_cartesian_mesh(4, 3, p=p, x0=0.1, x1=1.3, y0=-0.2, y1=0.9)
+    pa, ps = oracle.pattern(plain), oracle.pattern(split)
+    for k in ("row_ptr", "col_idx", "val_ptr", "dof_ptr"):
+        assert np.array_equal(getattr(pa, k), getattr(ps, k))
+    va, fa = oracle.assemble(plain, prob, pat=pa)
+    vs, fs = oracle.assemble(split, prob, pat=ps)
+    assert np.abs(va - vs).max() <= 1e-12 * np.abs(va).max()
+    assert np.abs(fa - fs).max() <= 1e-12 * np.abs(fa).max()
