@@ -446,13 +446,33 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     // ---- the row's offsets (scanned tile sums plus the element's prefix inside its tile)
     const int t0 = c / kPrepTile;
     const int4 cr = reinterpret_cast<const int4 *>(A.cnt)[c];
-    const int64_t pre_b = A.tile_off[3 * t0] + cr.x;
-    const int64_t pre_v = A.tile_off[3 * t0 + 1] + cr.y;
-    const int64_t pre_d = A.tile_off[3 * t0 + 2] + cr.z;
+    int64_t tb, tv, td;  // the tile's offsets
+    if (A.tile_sum) {
+        // no scan kernel ran: sum the sums of the tiles before this one (at most
+        // kInlineTiles of them; with at most 24 edges per polygon every prefix
+        // stays far below 2^31)
+        int sb = 0, sv = 0, sd = 0;
+        for (int t = lane; t < t0; t += 64) {
+            const int4 v = A.tile_sum[t];
+            sb += v.x;
+            sv += v.y;
+            sd += v.z;
+        }
+        tb = __builtin_amdgcn_readfirstlane(wave_sum_i(sb));
+        tv = __builtin_amdgcn_readfirstlane(wave_sum_i(sv));
+        td = __builtin_amdgcn_readfirstlane(wave_sum_i(sd));
+    } else {
+        tb = A.tile_off[3 * t0];
+        tv = A.tile_off[3 * t0 + 1];
+        td = A.tile_off[3 * t0 + 2];
+    }
+    const int64_t pre_b = tb + cr.x;
+    const int64_t pre_v = tv + cr.y;
+    const int64_t pre_d = td + cr.z;
     const int drank = cr.w & 255, dvoff = cr.w >> 8;
 
     // ---- loop edges, one per lane
-    int vid = 0, o = -3, rank = 0, voff = 0;
+    int vid = 0, o = -3, rank = 0, voff = 0, dupc = 0;
     bool first = false;
     double ex = 0.0, ey = 0.0;
     if (lane < nv) {
@@ -462,7 +482,8 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
         vid = er.vid;
         o = er.o;
         first = (er.rank & kEdgeFirst) != 0;
-        rank = er.rank & (kEdgeFirst - 1);
+        rank = er.rank & 255;
+        dupc = (er.rank >> kEdgeDupShift) & 255;
         voff = er.voff;
     }
     const uint64_t fm = __ballot(first);
@@ -481,7 +502,7 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
                 const int nblk = 1 + __popcll(fm);
                 A.row_ptr[c + 1] = pre_b + nblk;
                 A.dof_ptr[c + 1] = pre_d + NB;
-                A.val_ptr[pre_b + nblk] = A.tile_off[3 * n_tiles + 1];
+                A.val_ptr[pre_b + nblk] = A.tile_sum ? tv + A.tile_sum[t0].y : A.tile_off[3 * n_tiles + 1];
             }
         }
     }
@@ -490,13 +511,7 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     // groups: one per neighbour (led by its first edge) and one per boundary edge
     const uint64_t gmask = __ballot(first || (lane < nv && o < 0));
     const int ng = __popcll(gmask);
-    int dupc = 0;  // edges of the row towards this edge's neighbour
-    for (int k = 0; k < nv; ++k) {
-        const int ok = __shfl(o, k, 64);
-        if (ok == o && o >= 0) ++dupc;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) dupc = max(dupc, __shfl_xor(dupc, off, 64));
+    const int maxdup = __builtin_amdgcn_readfirstlane(wave_max_i(dupc));  // most edges shared with one neighbour
 
     const CellGeo g = A.geo[c];
     RowCtx R;
@@ -529,23 +544,19 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     R.o = o;
     R.voff = voff;
     R.dvoff = dvoff;
-    R.maxdup = max(dupc, 1);
+    R.maxdup = max(maxdup, 1);
     R.ng = ng;
     __shared__ T xlds[C::XL ? 4 * 64 * C::XW : 1];
     R.xs = C::XL ? xlds + (threadIdx.x >> 6) * 64 * C::XW : nullptr;
     R.gmask = gmask;
     {
-        // lane g gets the position of the g-th set bit of gmask
+        // lane g gets the position of the g-th set bit of gmask: a forward
+        // permutation sends group leaders to lanes 0 .. ng - 1 in order and the
+        // other lanes, in order, to ng .. 63
         const bool lead = (gmask >> lane) & 1ull;
         const int gidx = __popcll(gmask & ((1ull << lane) - 1ull));
-        int tab = 0;
-        for (int k = 0; k < nv; ++k) {
-            const int gk = __shfl(gidx, k, 64);
-            const bool lk = (gmask >> k) & 1ull;
-            if (lk && gk == lane) tab = k;
-        }
-        (void)lead;
-        R.gtab = tab;
+        const int dst = lead ? gidx : ng + (lane - gidx);
+        R.gtab = __builtin_amdgcn_ds_permute(dst << 2, lane);
     }
     R.ex = ex;
     R.ey = ey;

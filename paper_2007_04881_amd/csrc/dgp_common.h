@@ -7,7 +7,8 @@
 namespace dgp {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kMaxP = 4;          // 2D kernels are built for p = 1..4
+constexpr int kMaxP = 4;
+constexpr int kInlineTiles = 1024;  // 2D steps on at most this many tiles launch no scan kernel          // 2D kernels are built for p = 1..4
 constexpr int kMaxFaces2D = 24;   // faces per polygon handled by the preparation kernel
 constexpr int kPrepTile = 32;     // elements per preparation work-group (a tile)
 
@@ -58,10 +59,12 @@ struct alignas(16) EdgeRec {
     double x, y;   // start vertex of the edge
     int32_t vid;   // its global id (orders the edge's points canonically)
     int32_t o;     // neighbour across the edge, or minus the boundary code
-    int32_t rank;  // interior edge: position of the neighbour's block in the row (| kEdgeFirst on its first edge)
+    int32_t rank;  // interior edge: position of the neighbour's block in the row (bits 0-7), number of the
+                   // row's edges towards that neighbour (bits 8-15), | kEdgeFirst on its first edge
     int32_t voff;  // interior edge: value offset of that block inside the row
 };
 constexpr int32_t kEdgeFirst = 1 << 30;
+constexpr int kEdgeDupShift = 8;
 
 // Outputs of the preparation kernel.
 struct PrepOut {
@@ -69,7 +72,7 @@ struct PrepOut {
     int32_t *nbr;        // [loop entries] neighbour across each edge, or -boundary code
     EdgeRec *erec;       // [loop entries]
     int32_t *cnt;        // [n_cells][4] blocks, values, dofs before the element in its tile; diagonal rank | offset << 8
-    int64_t *tile_sum;   // [n_tiles][3]
+    int32_t *tile_sum;   // [n_tiles][4]: blocks, values and dofs of the tile, then 0
     int64_t *tile_off;   // [n_tiles + 1][3] exclusive prefix of the tile sums (totals last)
 };
 
@@ -254,6 +257,10 @@ struct AsmArgs {
     const int32_t *nbr;
     const int32_t *cnt;
     const int64_t *tile_off;
+    // non-null: no scan was launched; each row sums the tile sums before its
+    // own tile (2D meshes of at most kInlineTiles tiles)
+    const int4 *tile_sum = nullptr;
+    int32_t n_tiles = 0;
     const EdgeRec *erec;
     int64_t *row_ptr;
     int32_t *col_idx;

@@ -10,7 +10,8 @@
 namespace dgp {
 
 // Geometry, edge neighbours and row sizes, then the scan of the tile sums (two launches).
-void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st);
+// scan = false: the tile sums are left for the assembly kernel to sum (see AsmArgs::tile_sum)
+void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st, bool scan = true);
 
 // One wave per element row: pattern (if a.write_pattern) and values of rows
 // a.rows[0 .. n_rows) (all rows in order if a.rows is null), all of degree p;

@@ -18,6 +18,7 @@
 #include "dgp_common.h"
 #include "kernels.h"
 #include "rules_data.h"
+#include "wave.h"
 
 namespace dgp {
 
@@ -84,6 +85,7 @@ __device__ double max_a_on_triangle(const DevProblem &pr, const TrigCentre &tc, 
 
 __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut out) {
     __shared__ int s_cnt[CPB][3];
+    __shared__ double2 s_xy[CPB][kMaxFaces2D];  // each element's vertex loop
 
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
@@ -126,6 +128,14 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     }
 
     // ------------------------------------------------------------ geometry
+    // the loop goes to LDS once; the pair and triangle loops read it from there
+    // (an element's eight lanes belong to one wave)
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+        const int i = lane + G * q;
+        if (i < nv) s_xy[grp][i] = make_double2(xq[q], yq[q]);
+    }
+    wave_sync();
     double lox = 1e300, loy = 1e300, hix = -1e300, hiy = -1e300, a2 = 0.0, d2 = 0.0, amax = -1e300;
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
@@ -136,11 +146,11 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
             loy = fmin(loy, yi);
             hix = fmax(hix, xi);
             hiy = fmax(hiy, yi);
-            const int vn = m.cell_vtx[s + (i + 1 == nv ? 0 : i + 1)];
-            a2 += xi * m.y[vn] - m.x[vn] * yi;
+            const double2 vn = s_xy[grp][i + 1 == nv ? 0 : i + 1];
+            a2 += xi * vn.y - vn.x * yi;
             for (int j = i + 1; j < nv; ++j) {
-                const int vj = m.cell_vtx[s + j];
-                const double dx = xi - m.x[vj], dy = yi - m.y[vj];
+                const double2 vj = s_xy[grp][j];
+                const double dx = xi - vj.x, dy = yi - vj.y;
                 d2 = fmax(d2, dx * dx + dy * dy);
             }
         }
@@ -157,8 +167,8 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     const double ax0 = __shfl(xq[0], base, 64), ay0 = __shfl(yq[0], base, 64);  // vertex 0 sits in the group's first lane
     if (valid && pr.a1 != 0.0) {
         for (int t = lane; t + 2 < nv; t += G) {
-            const int v1 = m.cell_vtx[s + t + 1], v2 = m.cell_vtx[s + t + 2];
-            const double x1 = m.x[v1], y1 = m.y[v1], x2 = m.x[v2], y2 = m.y[v2];
+            const double2 p1 = s_xy[grp][t + 1], p2 = s_xy[grp][t + 2];
+            const double x1 = p1.x, y1 = p1.y, x2 = p2.x, y2 = p2.y;
             double am = p <= 2 ? max_a_on_triangle<4>(pr, tcen, ax0, ay0, x1, y1, x2, y2)
                       : p == 3 ? max_a_on_triangle<6>(pr, tcen, ax0, ay0, x1, y1, x2, y2)
                                : max_a_on_triangle<8>(pr, tcen, ax0, ay0, x1, y1, x2, y2);
@@ -170,8 +180,12 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     // ------------------------------------------------------ row size
     // a neighbour counts once, at its first face
     bool first[SLOTS];
+    int dup[SLOTS];  // edges of the loop towards the same neighbour
 #pragma unroll
-    for (int q = 0; q < SLOTS; ++q) first[q] = nb[q] >= 0;
+    for (int q = 0; q < SLOTS; ++q) {
+        first[q] = nb[q] >= 0;
+        dup[q] = 0;
+    }
 #pragma unroll
     for (int q2 = 0; q2 < SLOTS; ++q2) {
         for (int l2 = 0; l2 < G; ++l2) {
@@ -179,7 +193,10 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
             const int j = l2 + G * q2;
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q)
-                if (v == nb[q] && j < lane + G * q) first[q] = false;
+                if (v == nb[q]) {
+                    if (j < lane + G * q) first[q] = false;
+                    dup[q] += 1;
+                }
         }
     }
     int cnt = 0, szsum = 0;
@@ -233,7 +250,7 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
             r.y = yq[q];
             r.vid = vq[q];
             r.o = code[q];
-            r.rank = nb[q] >= 0 ? (rank[q] | (first[q] ? kEdgeFirst : 0)) : 0;
+            r.rank = nb[q] >= 0 ? (rank[q] | (dup[q] << kEdgeDupShift) | (first[q] ? kEdgeFirst : 0)) : 0;
             r.voff = nb[q] >= 0 ? voff[q] : 0;
             out.erec[s + f] = r;
         }
@@ -277,14 +294,15 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     if (threadIdx.x < 3) {
         int64_t sum = 0;
         for (int k = 0; k < CPB; ++k) sum += s_cnt[k][threadIdx.x];
-        out.tile_sum[3 * tile + threadIdx.x] = sum;
+        out.tile_sum[4 * tile + threadIdx.x] = (int)sum;  // at most 32 rows of 25 blocks of 15 x 15
+        if (threadIdx.x == 0) out.tile_sum[4 * tile + 3] = 0;
     }
 }
 
 // Exclusive scan of the tile sums (blocks, values, dofs) into tile_off, and
 // the totals after the last tile.  One work-group: each thread sums a run of
 // consecutive tiles, the runs are scanned in LDS, then written back.
-__global__ void __launch_bounds__(1024) k_tile_scan(const int64_t *__restrict__ tile_sum, int n_tiles,
+__global__ void __launch_bounds__(1024) k_tile_scan(const int32_t *__restrict__ tile_sum, int n_tiles,
                                                     int64_t *__restrict__ tile_off) {
     __shared__ int64_t sh[3][1024];
     const int t = threadIdx.x;
@@ -292,7 +310,7 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int64_t *__restrict__ 
     const int a = t * per, b = min(a + per, n_tiles);
     int64_t run[3] = {0, 0, 0};
     for (int i = a; i < b; ++i)
-        for (int q = 0; q < 3; ++q) run[q] += tile_sum[3 * i + q];
+        for (int q = 0; q < 3; ++q) run[q] += tile_sum[4 * i + q];
     for (int q = 0; q < 3; ++q) sh[q][t] = run[q];
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -308,16 +326,16 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int64_t *__restrict__ 
     for (int i = a; i < b; ++i)
         for (int q = 0; q < 3; ++q) {
             tile_off[3 * i + q] = acc[q];
-            acc[q] += tile_sum[3 * i + q];
+            acc[q] += tile_sum[4 * i + q];
         }
     if (t == 1023)
         for (int q = 0; q < 3; ++q) tile_off[3 * n_tiles + q] = sh[q][1023];
 }
 
-void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st) {
+void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st, bool scan) {
     const int n_tiles = (m.n_cells + kPrepTile - 1) / kPrepTile;
     hipLaunchKernelGGL(k_prep, dim3(n_tiles), dim3(WG), 0, st, m, pr, out);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, out.tile_sum, n_tiles, out.tile_off);
+    if (scan) hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, out.tile_sum, n_tiles, out.tile_off);
 }
 
 }  // namespace dgp

@@ -35,7 +35,6 @@ extern "C" __device__ __attribute__((const)) double __ockl_wfred_min_f64(double)
 extern "C" __device__ __attribute__((const)) double __ockl_wfred_max_f64(double);
 
 __device__ __forceinline__ int wave_min_i(int v) { return __ockl_wfred_min_i32(v); }
-__device__ __forceinline__ int wave_max_i(int v) { return __ockl_wfred_max_i32(v); }
 __device__ __forceinline__ double wave_min_d(double v) { return __ockl_wfred_min_f64(v); }
 __device__ __forceinline__ double wave_max_d(double v) { return __ockl_wfred_max_f64(v); }
 __device__ __forceinline__ double readlane_dbl(double v, int l) {

@@ -210,7 +210,7 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     const size_t o_erec = o_nbr + ((sizeof(int32_t) * (size_t)nnz_v + 255) & ~size_t(255));
     const size_t o_cnt = o_erec + ((sizeof(EdgeRec) * (size_t)nnz_v + 255) & ~size_t(255));
     const size_t o_tile = o_cnt + sizeof(int32_t) * 4 * (size_t)N;
-    const size_t o_off = o_tile + ((sizeof(int64_t) * 3 * (size_t)ctx->n_tiles + 255) & ~size_t(255));
+    const size_t o_off = o_tile + ((sizeof(int32_t) * 4 * (size_t)ctx->n_tiles + 255) & ~size_t(255));
     const size_t work_bytes = o_off + sizeof(int64_t) * 3 * (size_t)(ctx->n_tiles + 1);
     if (hipMalloc(&ctx->row_ptr, sizeof(int64_t) * (N + 1)) != hipSuccess ||
         hipMalloc(&ctx->col_idx, sizeof(int32_t) * nnzb_max) != hipSuccess ||
@@ -226,7 +226,7 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     ctx->prep.nbr = reinterpret_cast<int32_t *>(b + o_nbr);
     ctx->prep.erec = reinterpret_cast<EdgeRec *>(b + o_erec);
     ctx->prep.cnt = reinterpret_cast<int32_t *>(b + o_cnt);
-    ctx->prep.tile_sum = reinterpret_cast<int64_t *>(b + o_tile);
+    ctx->prep.tile_sum = reinterpret_cast<int32_t *>(b + o_tile);
     ctx->prep.tile_off = reinterpret_cast<int64_t *>(b + o_off);
     if (pmin != pmax) {
         // mixed degrees: one launch per degree over the elements of that degree (in id order)
@@ -387,11 +387,18 @@ static DevProblem neutral_problem() {
 static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
                                int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed);
 
-static void launch_prep_any(dgp_ctx *ctx, const DevProblem &dp, hipStream_t st) {
+// Steps that assemble values on a small 2D mesh launch no scan kernel: each
+// row of the assembly sums the tile sums before its tile.  Pattern-only steps
+// scan, since the host reads the totals.
+static bool inline_tiles(const dgp_ctx *ctx, int values) {
+    return ctx->dim == 2 && values && ctx->n_tiles <= kInlineTiles;
+}
+
+static void launch_prep_any(dgp_ctx *ctx, const DevProblem &dp, hipStream_t st, int values) {
     if (ctx->dim == 3)
         launch_prep3d(ctx->dm, dp, ctx->prep3, st);
     else
-        launch_prep(ctx->dm, dp, ctx->prep, st);
+        launch_prep(ctx->dm, dp, ctx->prep, st, !inline_tiles(ctx, values));
 }
 
 dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {
@@ -523,6 +530,8 @@ static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precis
     a.nbr = ctx->prep.nbr;
     a.cnt = ctx->prep.cnt;
     a.tile_off = ctx->prep.tile_off;
+    a.tile_sum = inline_tiles(ctx, values) ? reinterpret_cast<const int4 *>(ctx->prep.tile_sum) : nullptr;
+    a.n_tiles = ctx->n_tiles;
     a.erec = ctx->prep.erec;
     a.rows = nullptr;
     a.n_rows = (int32_t)ctx->n_cells;
@@ -559,7 +568,7 @@ static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precis
 static dgp_status enqueue_step(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
                                int write_pattern, void *vals, void *rhs, hipStream_t st, bool timed) {
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
-    launch_prep_any(ctx, dp, st);
+    launch_prep_any(ctx, dp, st, values);
     if (timed) HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
     dgp_status s = launch_assembly(ctx, dp, precision, rule_mode, values, write_pattern, vals, rhs, st);
     if (s) return s;
@@ -643,7 +652,7 @@ dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assem
     HIPCHK(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
-    for (int i = 0; i < reps; ++i) launch_prep_any(ctx, ctx->last_pr, st);
+    for (int i = 0; i < reps; ++i) launch_prep_any(ctx, ctx->last_pr, st, 1);
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
     for (int i = 0; i < reps; ++i) {
         dgp_status s = launch_assembly(ctx, ctx->last_pr, ctx->last_precision, ctx->last_rule, 1, 0, ctx->last_vals,
@@ -676,6 +685,8 @@ dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice) {
         a.nbr = ctx->prep.nbr;
         a.cnt = ctx->prep.cnt;
         a.tile_off = ctx->prep.tile_off;
+        a.tile_sum = inline_tiles(ctx, 1) ? reinterpret_cast<const int4 *>(ctx->prep.tile_sum) : nullptr;
+        a.n_tiles = ctx->n_tiles;
         a.erec = ctx->prep.erec;
         a.row_ptr = ctx->row_ptr;
         a.col_idx = ctx->col_idx;

@@ -82,6 +82,10 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// Sum and maximum of an int over the 64 lanes (DPP reductions), in every lane.
+__device__ __forceinline__ int wave_sum_i(int v) { return __ockl_wfred_add_i32(v); }
+__device__ __forceinline__ int wave_max_i(int v) { return __ockl_wfred_max_i32(v); }
+
 __device__ __forceinline__ double readlane_d(double v, int l) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
