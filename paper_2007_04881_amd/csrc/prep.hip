@@ -67,15 +67,19 @@ __device__ __forceinline__ double gmin_d(double v) {
     return v;
 }
 
+// max of a over this lane's share of the volume points (fan triangles of the
+// degree-DEG rule), the element's G lanes taking the points in turn
 template <int DEG>
-__device__ double max_a_on_triangle(const DevProblem &pr, const TrigCentre &tc, double x0, double y0, double x1,
-                                    double y1, double x2, double y2) {
+__device__ double max_a_points(const DevProblem &pr, const TrigCentre &tc, const double2 *loop, int nv, int lane) {
     const double *L = DEG == 4 ? c_tri4_l : DEG == 6 ? c_tri6_l : c_tri8_l;
-    const int n = DEG == 4 ? DGP_TRI4_N : DEG == 6 ? DGP_TRI6_N : DGP_TRI8_N;
+    constexpr int n = DEG == 4 ? DGP_TRI4_N : DEG == 6 ? DGP_TRI6_N : DGP_TRI8_N;
+    const double2 v0 = loop[0];
     double amax = -1e300;
-    for (int q = 0; q < n; ++q) {
-        double px = L[3 * q] * x0 + L[3 * q + 1] * x1 + L[3 * q + 2] * x2;
-        double py = L[3 * q] * y0 + L[3 * q + 1] * y1 + L[3 * q + 2] * y2;
+    for (int k = lane; k < (nv - 2) * n; k += G) {
+        const int t = k / n, q = k - t * n;
+        const double2 v1 = loop[t + 1], v2 = loop[t + 2];
+        const double px = L[3 * q] * v0.x + L[3 * q + 1] * v1.x + L[3 * q + 2] * v2.x;
+        const double py = L[3 * q] * v0.y + L[3 * q + 1] * v1.y + L[3 * q + 2] * v2.y;
         amax = fmax(amax, coef_a_near(pr, tc, px, py));
     }
     return amax;
@@ -163,22 +167,33 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     d2 = gmax_d(d2);
     // sin/cos at the box centre, then abar over the volume points by angle addition from it
     const double hxb = hix - lox, hyb = hiy - loy;
-    const TrigCentre tcen = trig_centre(pr, 0.5 * (lox + hix), 0.5 * (loy + hiy), 0.5 * sqrt(hxb * hxb + hyb * hyb));
-    const double ax0 = __shfl(xq[0], base, 64), ay0 = __shfl(yq[0], base, 64);  // vertex 0 sits in the group's first lane
-    if (valid && pr.a1 != 0.0) {
-        for (int t = lane; t + 2 < nv; t += G) {
-            const double2 p1 = s_xy[grp][t + 1], p2 = s_xy[grp][t + 2];
-            const double x1 = p1.x, y1 = p1.y, x2 = p2.x, y2 = p2.y;
-            double am = p <= 2 ? max_a_on_triangle<4>(pr, tcen, ax0, ay0, x1, y1, x2, y2)
-                      : p == 3 ? max_a_on_triangle<6>(pr, tcen, ax0, ay0, x1, y1, x2, y2)
-                               : max_a_on_triangle<8>(pr, tcen, ax0, ay0, x1, y1, x2, y2);
-            amax = fmax(amax, am);
-        }
+    // sin/cos(pi x0) on even lanes, sin/cos(pi y0) on odd lanes, then swapped inside the pair
+    TrigCentre tcen;
+    tcen.x0 = 0.5 * (lox + hix);
+    tcen.y0 = 0.5 * (loy + hiy);
+    tcen.near = kPi * 0.5 * sqrt(hxb * hxb + hyb * hyb) <= kNearT;
+    tcen.sx = tcen.sy = 0.0;
+    tcen.cx = tcen.cy = 1.0;
+    if (needs_trig(pr)) {
+        const bool odd = lane & 1;
+        double s1, c1;
+        sincospi(odd ? tcen.y0 : tcen.x0, &s1, &c1);
+        const double s2 = dpp_d<0xB1>(s1), c2 = dpp_d<0xB1>(c1);
+        tcen.sx = odd ? s2 : s1;
+        tcen.cx = odd ? c2 : c1;
+        tcen.sy = odd ? s1 : s2;
+        tcen.cy = odd ? c1 : c2;
     }
+    if (valid && pr.a1 != 0.0)
+        amax = p <= 2 ? max_a_points<4>(pr, tcen, s_xy[grp], nv, lane)
+             : p == 3 ? max_a_points<6>(pr, tcen, s_xy[grp], nv, lane)
+                      : max_a_points<8>(pr, tcen, s_xy[grp], nv, lane);
     amax = gmax_d(amax);
 
     // ------------------------------------------------------ row size
     // a neighbour counts once, at its first face
+    // loop slots used by some element of this wave (most polygons fill one)
+    const int nvmax = __builtin_amdgcn_readfirstlane(wave_max_i(nv));
     bool first[SLOTS];
     int dup[SLOTS];  // edges of the loop towards the same neighbour
 #pragma unroll
@@ -188,6 +203,7 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     }
 #pragma unroll
     for (int q2 = 0; q2 < SLOTS; ++q2) {
+        if (G * q2 >= nvmax) break;
         for (int l2 = 0; l2 < G; ++l2) {
             const int v = __shfl(nb[q2], base + l2, 64);
             const int j = l2 + G * q2;
@@ -223,6 +239,7 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     int drank = 0, dvoff = 0;
 #pragma unroll
     for (int q2 = 0; q2 < SLOTS; ++q2) {
+        if (G * q2 >= nvmax) break;
         for (int l2 = 0; l2 < G; ++l2) {
             const int v = __shfl(nb[q2], base + l2, 64);
             const int vf = __shfl((int)first[q2], base + l2, 64);
