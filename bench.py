@@ -38,6 +38,32 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
+def _traffic_entry(variant):
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_digest():
+        return None
+    return t.get("by_variant", {}).get(str(variant))
+
+
+# vector issue rate: 1,024 SIMDs x 2.4 GHz, one wave64 VALU instruction per 4 cycles
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
+
+
+def valu_issue(variant, kernel_ms):
+    """The assembly kernel's VALU instructions per launch (SQ_INSTS_VALU of the
+    committed counter run, same sources and variant) against the chip's vector
+    issue rate over the measured launch time; None if the sources changed."""
+    v = _traffic_entry(variant)
+    if not v or "valu_insts" not in v:
+        return None
+    issue_ms = v["valu_insts"] / VALU_ISSUE_PER_S * 1e3
+    return {"valu_insts_per_launch": v["valu_insts"], "issue_ms": issue_ms, "frac": issue_ms / kernel_ms}
+
+
 def measured_traffic(variant):
     """HBM bytes per launch of the assembly kernel (register-budget variant
     `variant`) from the committed counter runs (FETCH_SIZE + WRITE_SIZE, scaled
@@ -349,7 +375,8 @@ def main():
         "kernel_ms": avg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(alt),
-                     "kernel": f"k_row2d<float,2,2,false,true,{alt}>", "algorithmic_bytes": abytes},
+                     "kernel": f"k_row2d<float,2,2,false,true,{alt}>", "algorithmic_bytes": abytes,
+                     "valu_issue": valu_issue(alt, avg["assemble"])},
         "autotuned_variant": alt,
     }
     ctx.close()

@@ -248,23 +248,48 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             PointCoef<T> pc;
             pc.zero();
             double xi = 0.0, eta = 0.0, xin = 0.0, etan = 0.0;
-            if (vol && !R.red) {
+            // the lane's point and weight: a fan sub-triangle point, or point gq
+            // of its edge (canonical order: lower vertex id first)
+            const bool vpt = vol && !R.red;
+            double px = 0.0, py = 0.0, W = 0.0, nx = 0.0, ny = 0.0, up = 0.0;
+            if (vpt) {
                 const int qi = q - tri * C::NQT;
                 const double area = 0.5 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
                 const double l0 = R_::l(3 * qi), l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
-                const double px = l0 * X0 + l1 * X1 + l2 * X2, py = l0 * Y0 + l1 * Y1 + l2 * Y2;
-                const double W = R_::w(qi) * area;
-                const PointData pd = point_data_near(pr, tc, px, py, SL == 0);
+                px = l0 * X0 + l1 * X1 + l2 * X2;
+                py = l0 * Y0 + l1 * Y1 + l2 * Y2;
+                W = R_::w(qi) * area;
+            } else if (epnt) {
+                const bool fwd = V1 < V2;
+                const double xa = fwd ? X1 : X2, ya = fwd ? Y1 : Y2;
+                const double tx = (fwd ? X2 : X1) - xa, ty = (fwd ? Y2 : Y1) - ya;
+                const double len = sqrt(tx * tx + ty * ty);
+                const double dl = (fwd ? 1.0 : -1.0) / len;
+                nx = ty * dl;  // outward for a CCW loop
+                ny = -tx * dl;
+                const double bn = pr.bx * nx + pr.by * ny;
+                up = bn < 0.0 ? bn : 0.0;
+                const int goff = c_gl_off[ngf - 1];
+                const double tq = c_gl_t[goff + gq];
+                W = c_gl_w[goff + gq] * len;
+                px = xa + tq * tx;
+                py = ya + tq * ty;
+            }
+            // coefficient and load data, one evaluation for the element points
+            // and the interior edge points (sin/cos by angle addition from the centre)
+            PointData pdn{};
+            if (vpt || (epnt && og >= 0)) pdn = point_data_near(pr, tc, px, py, SL == 0);
+            if (vpt) {
                 xi = (px - bx.mx) * bx.cx;
                 eta = (py - bx.my) * bx.cy;
-                pc.a0 = T(W * bx.cx * bx.cx * pd.a);
-                pc.a1 = T(W * bx.cy * bx.cy * pd.a);
+                pc.a0 = T(W * bx.cx * bx.cx * pdn.a);
+                pc.a1 = T(W * bx.cy * bx.cy * pdn.a);
                 if (ADV) {
                     pc.c0 = T(W * pr.bx * bx.cx);
                     pc.c1 = T(W * pr.by * bx.cy);
                     pc.c2 = T(W * pr.c);
                 }
-                pc.r2 = T(W * pd.f);
+                pc.r2 = T(W * pdn.f);
             } else if (vol) {
                 // reduced rule: node q of the element's accepted rule (box coordinates)
                 xi = A.qr_nodes[(int64_t)c * 2 * kQrNodes + 2 * q];
@@ -279,24 +304,13 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                     pc.c2 = T(W * pr.c);
                 }
             } else if (epnt) {
-                // edge (v_fk, v_fk+1); points in canonical order (lower vertex id first)
-                const bool fwd = V1 < V2;
-                const double xa = fwd ? X1 : X2, ya = fwd ? Y1 : Y2;
-                const double tx = (fwd ? X2 : X1) - xa, ty = (fwd ? Y2 : Y1) - ya;
-                const double len = sqrt(tx * tx + ty * ty);
-                const double dir = fwd ? 1.0 : -1.0;
-                const double nx = dir * ty / len, ny = -dir * tx / len;  // outward for a CCW loop
-                const double bn = pr.bx * nx + pr.by * ny;
-                const double up = bn < 0.0 ? bn : 0.0;
-                const int goff = c_gl_off[ngf - 1];
-                const double tq = c_gl_t[goff + gq], w = c_gl_w[goff + gq] * len;
-                const double px = xa + tq * tx, py = ya + tq * ty;
+                const double w = W;
                 const double cnx = bx.cx * nx, cny = bx.cy * ny;
                 xi = (px - bx.mx) * bx.cx;
                 eta = (py - bx.my) * bx.cy;
                 if (og >= 0) {
                     const double sigma = pr.c_sigma * (R.pen_r > pen_o ? R.pen_r : pen_o);
-                    const double ha = -0.5 * w * coef_a_near(pr, tc, px, py), hs = (sigma - up) * w;
+                    const double ha = -0.5 * w * pdn.a, hs = (sigma - up) * w;
                     pc.b0 = T(ha * cnx);
                     pc.b1 = T(ha * cny);
                     pc.c0 = T(ha * cnx);
@@ -437,7 +451,7 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     const DevMesh &m = A.m;
     const int lane = threadIdx.x & 63;
     // the row index is uniform across the wave: keep it (and what derives from it) in scalar registers
-    const int wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wid = xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wid >= A.n_rows) return;
     const int c = A.rows ? __builtin_amdgcn_readfirstlane(A.rows[wid]) : wid;
     const int64_t s = m.cell_ptr[c];

@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
     const int base = threadIdx.x & ~(G - 1);  // first lane of this element's group
-    const int tile = blockIdx.x;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
     const int c = tile * CPB + grp;
     const bool valid = c < m.n_cells;
     int64_t s = 0;

@@ -82,6 +82,15 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// Work-groups are dealt to the 8 XCDs (each with its own L2) in turn: block b
+// runs on XCD b mod 8.  This renumbering gives XCD x one contiguous range of
+// the grid's work (the ranges differ in length by at most one), so spatial
+// neighbours, numbered close together, are mostly read through the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // Sum and maximum of an int over the 64 lanes (DPP reductions), in every lane.
 __device__ __forceinline__ int wave_sum_i(int v) { return __ockl_wfred_add_i32(v); }
 __device__ __forceinline__ int wave_max_i(int v) { return __ockl_wfred_max_i32(v); }
