@@ -54,9 +54,12 @@ struct RowCfg {
     static constexpr int NB = nb2d(P);
     static constexpr int NBN = nb2d(PN);
     static constexpr int NB2 = NB * NB;
-    static constexpr int JS = sizeof(T) == 4 ? (P <= 2 ? NB : P == 3 ? 5 : 3) : (P == 1 ? 3 : P == 2 ? 3 : 2);
+    // MF: the element block is a matrix-core product (FP32, p >= 3: 10 x 10 and
+    // 15 x 15 blocks fill enough of a 16 x 16 tile); no column slices then
+    static constexpr bool MF = sizeof(T) == 4 && P >= 3;
+    static constexpr int JS = MF ? NB : sizeof(T) == 4 ? (P <= 2 ? NB : P == 3 ? 5 : 3) : (P == 1 ? 3 : P == 2 ? 3 : 2);
     static constexpr int NSL = (NB + JS - 1) / JS;
-    static constexpr int ED = NB * JS;  // element-block entries per slice
+    static constexpr int ED = MF ? 0 : NB * JS;  // element-block entries per slice held in registers
     static constexpr int E = ED + NB;   // with the load vector
     static_assert(E <= 64, "one entry per lane after the reduction");
     static constexpr int PF = P > PN ? P : PN;
@@ -89,6 +92,44 @@ struct PointCoef {
         a0 = b0 = a1 = b1 = c0 = c1 = c2 = x0 = x1 = r0 = r1 = r2 = T(0);
     }
 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Element block on the matrix cores: D_ij = sum over (point, a) of u_a(i) t_a(j)
+// with the test terms u = (d/dxi, d/deta, value) of basis i and the trial terms
+// t_a(j) of the rank-3 form.  The 64 points of a pass go through LDS in two
+// halves of 32 lanes, 96 rows of (u | t) each, 16 columns (the basis index,
+// padding unused); each half is 24 steps of v_mfma_f32_16x16x4f32 (A: row
+// lane % 16, k lane / 16; B: k lane / 16, column lane % 16; accumulator r of
+// lane l: D[4 (l / 16) + r][l % 16]).  Padding rows and columns only reach
+// entries that are never written.
+template <typename T, int P>
+__device__ __forceinline__ void mf_element(float *lds, int lane, const Eval<T, P> &ev, const PointCoef<T> &pc,
+                                           f32x4 &acc) {
+    constexpr int NB = nb2d(P);
+    float *U = lds, *Tt = lds + 96 * 16;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if ((lane >> 5) == h) {
+            const int k0 = 3 * (lane & 31);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                U[(k0 + 0) * 16 + j] = ev.g0[j];
+                U[(k0 + 1) * 16 + j] = ev.g1[j];
+                U[(k0 + 2) * 16 + j] = ev.v[j];
+                Tt[(k0 + 0) * 16 + j] = fmat(pc.a0, ev.g0[j], pc.b0 * ev.v[j]);
+                Tt[(k0 + 1) * 16 + j] = fmat(pc.a1, ev.g1[j], pc.b1 * ev.v[j]);
+                Tt[(k0 + 2) * 16 + j] = fmat(pc.c0, ev.g0[j], fmat(pc.c1, ev.g1[j], pc.c2 * ev.v[j]));
+            }
+        }
+        wave_sync();
+        const int r = lane >> 4, c = lane & 15;
+#pragma unroll 4
+        for (int s = 0; s < 24; ++s)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(U[(4 * s + r) * 16 + c], Tt[(4 * s + r) * 16 + c], acc, 0, 0, 0);
+        wave_sync();  // the next half rewrites the table
+    }
+}
 
 // Everything a slice of the row needs, computed once per row.
 struct RowCtx {
@@ -196,6 +237,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
     T acc[64];
 #pragma unroll
     for (int e = 0; e < 64; ++e) acc[e] = T(0);  // [0, ED): element block slice, [ED, ED + NB): load
+    f32x4 accm = {0.0f, 0.0f, 0.0f, 0.0f};      // MF kernels: the element block on the matrix cores
 
     for (int base = 0; base < Qtot; base += 64) {
         const int q = base + lane;
@@ -339,8 +381,9 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             }
             Eval<T, P> ev;
             ev.at(T(xi), T(eta));
+            if constexpr (C::MF) mf_element<T, P>(static_cast<float *>(R.xs), lane, ev, pc, accm);
 #pragma unroll
-            for (int jj = 0; jj < JS; ++jj) {
+            for (int jj = 0; jj < (C::MF ? 0 : JS); ++jj) {
                 const int j = j0 + jj;
                 if (j < NB) {
                     const T t0 = fmat(pc.a0, ev.g0[j], pc.b0 * ev.v[j]);
@@ -431,6 +474,15 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
     } else if (SL == 0 && lane < C::E) {
         const int i = lane - ED;
         rhs[R.pre_d + i] = T(double(acc[0]) * (c_norm[i] * R.isq));
+    }
+    if constexpr (C::MF) {
+        const int j = lane & 15;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 4 * (lane >> 4) + r;
+            if (i < NB && j < NB)
+                vals[R.pre_v + R.dvoff + i * NB + j] = T(double(accm[r]) * (c_norm[i] * c_norm[j] * R.isq * R.isq));
+        }
     }
 }
 
@@ -560,8 +612,8 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     R.dvoff = dvoff;
     R.maxdup = max(maxdup, 1);
     R.ng = ng;
-    __shared__ T xlds[C::XL ? 4 * 64 * C::XW : 1];
-    R.xs = C::XL ? xlds + (threadIdx.x >> 6) * 64 * C::XW : nullptr;
+    __shared__ T xlds[C::XL ? 4 * 64 * C::XW : C::MF ? 4 * 2 * 96 * 16 : 1];
+    R.xs = C::XL ? xlds + (threadIdx.x >> 6) * 64 * C::XW : C::MF ? xlds + (threadIdx.x >> 6) * 2 * 96 * 16 : nullptr;
     R.gmask = gmask;
     {
         // lane g gets the position of the g-th set bit of gmask: a forward
