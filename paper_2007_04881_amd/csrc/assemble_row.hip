@@ -38,6 +38,7 @@
 // penalty are FP64; the point coefficients are rounded once to T and the
 // basis is evaluated in T.  The basis normalisation s_i s'_j is applied to the
 // finished sums in FP64.
+#include <type_traits>
 #include <utility>
 
 #include "asm_common.h"
@@ -54,9 +55,10 @@ struct RowCfg {
     static constexpr int NB = nb2d(P);
     static constexpr int NBN = nb2d(PN);
     static constexpr int NB2 = NB * NB;
-    // MF: the element block is a matrix-core product (FP32, p >= 3: 10 x 10 and
+    // MF: the element block is a matrix-core product (p >= 3: 10 x 10 and
     // 15 x 15 blocks fill enough of a 16 x 16 tile); no column slices then
-    static constexpr bool MF = sizeof(T) == 4 && P >= 3;
+    static constexpr bool MF = P >= 3;
+    static constexpr int MFW = sizeof(T) == 4 ? 2 * 96 * 16 : 2 * 48 * 16;  // LDS table per wave (T elements)
     static constexpr int JS = MF ? NB : sizeof(T) == 4 ? (P <= 2 ? NB : P == 3 ? 5 : 3) : (P == 1 ? 3 : P == 2 ? 3 : 2);
     static constexpr int NSL = (NB + JS - 1) / JS;
     static constexpr int ED = MF ? 0 : NB * JS;  // element-block entries per slice held in registers
@@ -94,24 +96,43 @@ struct PointCoef {
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+using MfAcc = std::conditional_t<sizeof(T) == 4, f32x4, f64x4>;
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // Element block on the matrix cores: D_ij = sum over (point, a) of u_a(i) t_a(j)
 // with the test terms u = (d/dxi, d/deta, value) of basis i and the trial terms
-// t_a(j) of the rank-3 form.  The 64 points of a pass go through LDS in two
-// halves of 32 lanes, 96 rows of (u | t) each, 16 columns (the basis index,
-// padding unused); each half is 24 steps of v_mfma_f32_16x16x4f32 (A: row
-// lane % 16, k lane / 16; B: k lane / 16, column lane % 16; accumulator r of
-// lane l: D[4 (l / 16) + r][l % 16]).  Padding rows and columns only reach
-// entries that are never written.
+// t_a(j) of the rank-3 form.  The 64 points of a pass go through LDS in groups
+// of lanes (two of 32 in FP32, four of 16 in FP64: 12 KB per wave either way),
+// 3 rows of u and of t per lane, 16 columns (the basis index, padding unused);
+// each group is K / 4 steps of the 16 x 16 x 4 matrix instruction (A: row
+// lane % 16, k lane / 16; B: k lane / 16, column lane % 16).  Accumulator r of
+// lane l holds D[4 (l / 16) + r][l % 16] in FP32 and D[4 r + l / 16][l % 16]
+// in FP64 (mf_row).  Padding rows and columns only reach entries that are
+// never written.
+template <typename T>
+__device__ __forceinline__ int mf_row(int lane, int r) {
+    return sizeof(T) == 4 ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
+}
+
 template <typename T, int P>
-__device__ __forceinline__ void mf_element(float *lds, int lane, const Eval<T, P> &ev, const PointCoef<T> &pc,
-                                           f32x4 &acc) {
+__device__ __forceinline__ void mf_element(T *lds, int lane, const Eval<T, P> &ev, const PointCoef<T> &pc,
+                                           MfAcc<T> &acc) {
     constexpr int NB = nb2d(P);
-    float *U = lds, *Tt = lds + 96 * 16;
+    constexpr int NGR = sizeof(T) == 4 ? 2 : 4;  // lane groups staged in turn
+    constexpr int LG = 64 / NGR;                 // lanes per group
+    constexpr int KR = 3 * LG;                   // rows of u (and of t) per group
+    T *U = lds, *Tt = lds + KR * 16;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if ((lane >> 5) == h) {
-            const int k0 = 3 * (lane & 31);
+    for (int g = 0; g < NGR; ++g) {
+        if (lane / LG == g) {
+            const int k0 = 3 * (lane % LG);
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 U[(k0 + 0) * 16 + j] = ev.g0[j];
@@ -125,9 +146,8 @@ __device__ __forceinline__ void mf_element(float *lds, int lane, const Eval<T, P
         wave_sync();
         const int r = lane >> 4, c = lane & 15;
 #pragma unroll 4
-        for (int s = 0; s < 24; ++s)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(U[(4 * s + r) * 16 + c], Tt[(4 * s + r) * 16 + c], acc, 0, 0, 0);
-        wave_sync();  // the next half rewrites the table
+        for (int s = 0; s < KR / 4; ++s) acc = mfma16(U[(4 * s + r) * 16 + c], Tt[(4 * s + r) * 16 + c], acc);
+        wave_sync();  // the next group rewrites the table
     }
 }
 
@@ -237,7 +257,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
     T acc[64];
 #pragma unroll
     for (int e = 0; e < 64; ++e) acc[e] = T(0);  // [0, ED): element block slice, [ED, ED + NB): load
-    f32x4 accm = {0.0f, 0.0f, 0.0f, 0.0f};      // MF kernels: the element block on the matrix cores
+    MfAcc<T> accm = {T(0), T(0), T(0), T(0)};   // MF kernels: the element block on the matrix cores
 
     for (int base = 0; base < Qtot; base += 64) {
         const int q = base + lane;
@@ -381,7 +401,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             }
             Eval<T, P> ev;
             ev.at(T(xi), T(eta));
-            if constexpr (C::MF) mf_element<T, P>(static_cast<float *>(R.xs), lane, ev, pc, accm);
+            if constexpr (C::MF) mf_element<T, P>(static_cast<T *>(R.xs), lane, ev, pc, accm);
 #pragma unroll
             for (int jj = 0; jj < (C::MF ? 0 : JS); ++jj) {
                 const int j = j0 + jj;
@@ -479,7 +499,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
         const int j = lane & 15;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int i = 4 * (lane >> 4) + r;
+            const int i = mf_row<T>(lane, r);
             if (i < NB && j < NB)
                 vals[R.pre_v + R.dvoff + i * NB + j] = T(double(accm[r]) * (c_norm[i] * c_norm[j] * R.isq * R.isq));
         }
@@ -612,8 +632,8 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     R.dvoff = dvoff;
     R.maxdup = max(maxdup, 1);
     R.ng = ng;
-    __shared__ T xlds[C::XL ? 4 * 64 * C::XW : C::MF ? 4 * 2 * 96 * 16 : 1];
-    R.xs = C::XL ? xlds + (threadIdx.x >> 6) * 64 * C::XW : C::MF ? xlds + (threadIdx.x >> 6) * 2 * 96 * 16 : nullptr;
+    __shared__ T xlds[C::XL ? 4 * 64 * C::XW : C::MF ? 4 * C::MFW : 1];
+    R.xs = C::XL ? xlds + (threadIdx.x >> 6) * 64 * C::XW : C::MF ? xlds + (threadIdx.x >> 6) * C::MFW : nullptr;
     R.gmask = gmask;
     {
         // lane g gets the position of the g-th set bit of gmask: a forward
