@@ -38,7 +38,7 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def _traffic_entry(variant):
+def _traffic_entry(cfg):
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -46,37 +46,31 @@ def _traffic_entry(variant):
         return None
     if t.get("source_sha256") != kernel_source_digest():
         return None
-    return t.get("by_variant", {}).get(str(variant))
+    return t.get("by_config", {}).get(str(cfg))
 
 
 # vector issue rate: 1,024 SIMDs x 2.4 GHz, one wave64 VALU instruction per 4 cycles
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
-def valu_issue(variant, kernel_ms):
+def valu_issue(cfg, kernel_ms):
     """The assembly kernel's VALU instructions per launch (SQ_INSTS_VALU of the
-    committed counter run, same sources and variant) against the chip's vector
-    issue rate over the measured launch time; None if the sources changed."""
-    v = _traffic_entry(variant)
+    committed counter run, same sources and launch configuration) against the
+    chip's vector issue rate over the measured launch time; None if the sources
+    changed."""
+    v = _traffic_entry(cfg)
     if not v or "valu_insts" not in v:
         return None
     issue_ms = v["valu_insts"] / VALU_ISSUE_PER_S * 1e3
     return {"valu_insts_per_launch": v["valu_insts"], "issue_ms": issue_ms, "frac": issue_ms / kernel_ms}
 
 
-def measured_traffic(variant):
-    """HBM bytes per launch of the assembly kernel (register-budget variant
-    `variant`) from the committed counter runs (FETCH_SIZE + WRITE_SIZE, scaled
-    by a copy kernel of known size), or None if the kernel sources changed since
-    they were taken."""
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if t.get("source_sha256") != kernel_source_digest():
-        return None
-    v = t.get("by_variant", {}).get(str(variant))
+def measured_traffic(cfg):
+    """HBM bytes per launch of the assembly kernel in launch configuration cfg
+    from the committed counter runs (FETCH_SIZE + WRITE_SIZE, scaled by a copy
+    kernel of known size), or None if the kernel sources changed since they
+    were taken."""
+    v = _traffic_entry(cfg)
     return v.get("bytes_per_launch") if v else None
 
 
@@ -209,7 +203,7 @@ def mixed_degree_study(D, torch, steps, warmup):
         asm_t = ctx.time_kernels(10)[1]
         out[name] = {"ms_per_step": ms, "block_nnz_per_s": info.nnzb / (ms * 1e-3),
                      "kernel_ms": {"prep": prep_ms, "assemble": asm_ms},
-                     "autotuned": {"row_kernel_variant_by_degree": choice[1 if prec == D.F32 else 0][1:],
+                     "autotuned": {"launch_cfg_by_degree": choice[1 if prec == D.F32 else 0][1:],
                                    "ms_per_step": ms_t, "assemble_kernel_ms": asm_t}}
         del vals, rhs
     ctx.close()
@@ -256,7 +250,12 @@ def traffic_probe(D, torch):
     vals, rhs = ctx.outputs(D.F32)
     for _ in range(10):
         ctx.run(params, D.F32, vals, rhs)
-    ctx.autotune(200)  # dispatches both register-budget variants of the row kernel
+    # 10 steps in each launch configuration, in order (register budget r, row
+    # order s: cfg = r + 2 s); the counter summary maps dispatches to them
+    for cfg in range(4):
+        ctx.set_launch(D.F32, 2, cfg)
+        for _ in range(10):
+            ctx.run(params, D.F32, vals, rhs)
     torch.cuda.synchronize()
     x = torch.empty(16 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 64 MiB
     y = torch.empty_like(x)
@@ -278,8 +277,8 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the polyhedral (3D) workload")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree 262,144-cell workload")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="for HBM counter runs: 10 whole steps of the headline workload, the launch tuning (both "
-                         "register-budget variants of the row kernel), then 10 copies of a "
+                    help="for HBM counter runs: 10 whole steps of the headline workload, 10 more in each of the "
+                         "four launch configurations, then 10 copies of a "
                          "64 MiB tensor (the copy calibrates FETCH_SIZE / WRITE_SIZE); prints no JSON")
     ap.add_argument("--train-polygons", type=int, default=1_000_000)
     ap.add_argument("--train-epochs", type=int, default=30)
@@ -314,8 +313,8 @@ def main():
     single_ms = (time.perf_counter() - t0) * 1e3
 
     # launch tuning (outside the timed region): the row kernel's register budget
-    choice = ctx.autotune(200)
-    alt = choice[1][2]
+    cfg = ctx.autotune(200)[1][2]
+    alt = cfg & 1
 
     # the timed steps: the whole path, one asynchronous dgp_run per step, back to
     # back on the context stream (the host enqueues a step in ~10 us, well
@@ -374,10 +373,11 @@ def main():
         "single_shot_ms": single_ms,
         "kernel_ms": avg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(alt),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg),
                      "kernel": f"k_row2d<float,2,2,false,true,{alt}>", "algorithmic_bytes": abytes,
-                     "valu_issue": valu_issue(alt, avg["assemble"])},
-        "autotuned_variant": alt,
+                     "valu_issue": valu_issue(cfg, avg["assemble"])},
+        "launch_config": {"cfg": cfg, "register_budget": "one more wave per SIMD" if alt else "default",
+                          "row_order": "(degree, sub-triangles) bins" if cfg & 2 else "cell id"},
     }
     ctx.close()
     if not args.no_reduced:

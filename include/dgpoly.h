@@ -182,17 +182,26 @@ dgp_status dgp_kernel_ms(dgp_ctx *ctx, const char *name, float *ms);
  * must still be allocated).  Synchronous. */
 dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assemble_ms);
 
-/* Launch tuning per degree bin (the rows grouped by degree, Section 3.1's
- * grouping of elements by p).  For the last dgp_run / dgp_assemble on a 2D
- * mesh with plain rules, times each degree bin's row kernel in its two
- * register budgets (the default, and one more wave per SIMD) within about
- * budget_ms milliseconds of device time and keeps the faster for later
- * launches of that precision and degree.  Values of the last call's output
- * buffers are rewritten (they must still be allocated).  3D meshes and
- * reduced rules have a single configuration (nothing changes).  choice: NULL
- * or int32[2][5], the variant in use per [FP64, FP32][degree 0..4] on return.
- * Synchronous.  DGP_EINVAL if budget_ms < 1, DGP_ESTATE before an assembly. */
+/* Launch tuning per degree bin (Section 3.1 groups the elements by p; the
+ * upload also sorts each degree's rows by their number of fan sub-triangles,
+ * the bins (p, n_sub)).  A 2D launch configuration is cfg = r + 2 s with
+ * r = 1 for the row kernel's larger occupancy (one more wave per SIMD, fewer
+ * registers) and s = 1 for the rows in (p, n_sub) order instead of id order.
+ * For the last dgp_run / dgp_assemble on a 2D mesh with plain rules, times the
+ * four configurations of each degree bin within about budget_ms milliseconds of
+ * device time and keeps the fastest for later launches of that precision and
+ * degree.  Results do not depend on the configuration.  Values of the last
+ * call's output buffers are rewritten (they must still be allocated).  3D
+ * meshes and reduced rules have a single configuration (nothing changes).
+ * choice: NULL or int32[2][5], cfg in use per [FP64, FP32][degree 0..4] on
+ * return.  Synchronous.  DGP_EINVAL if budget_ms < 1, DGP_ESTATE before an
+ * assembly. */
 dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice);
+
+/* Set the 2D launch configuration cfg (0..3, as for dgp_autotune) of one
+ * precision and degree without timing, for reproducible launches.
+ * DGP_EINVAL for a bad precision or cfg, DGP_EUNSUPPORTED for p outside 1..4. */
+dgp_status dgp_set_launch(dgp_ctx *ctx, int precision, int p, int cfg);
 
 /* ---------------------------------------------------------------------
  * Reduced volume rules for polygons (an extension of Section 3: the paper

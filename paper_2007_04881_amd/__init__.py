@@ -68,7 +68,7 @@ class TrainStats(C.Structure):
 
 EXPORTS = ["dgp_create", "dgp_destroy", "dgp_set_stream", "dgp_last_error", "dgp_mesh_upload", "dgp_pattern",
            "dgp_pattern_copy", "dgp_assemble", "dgp_run", "dgp_graph_capture", "dgp_graph_launch",
-           "dgp_set_timing", "dgp_kernel_ms", "dgp_time_kernels", "dgp_autotune", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
+           "dgp_set_timing", "dgp_kernel_ms", "dgp_time_kernels", "dgp_autotune", "dgp_set_launch", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
            "dgp_qrule_cell_data", "dgp_train_polygons", "dgp_mlp_forward", "dgp_mlp_loss_grad", "dgp_adam_step",
            "dgp_mlp_train"]
 
@@ -114,6 +114,7 @@ def lib():
         L.dgp_kernel_ms.argtypes = [C.c_void_p, C.c_char_p, C.POINTER(C.c_float)]
         L.dgp_time_kernels.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.dgp_autotune.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.dgp_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
         _lib = L
     return _lib
 
@@ -255,11 +256,16 @@ class Context:
         return a.value, b.value
 
     def autotune(self, budget_ms=200):
-        """Pick each degree bin's row-kernel register budget for the last
-        assembly's precision; returns the [FP64, FP32][degree] choice table."""
+        """Pick each degree bin's 2D launch configuration (cfg = register budget
+        + 2 * row order) for the last assembly's precision; returns the
+        [FP64, FP32][degree] table of configurations in use."""
         out = (C.c_int32 * 10)()
         self._check(lib().dgp_autotune(self._h, int(budget_ms), C.cast(out, C.c_void_p)), "dgp_autotune")
         return [[out[q * 5 + p] for p in range(5)] for q in range(2)]
+
+    def set_launch(self, precision, p, cfg):
+        """Set the 2D launch configuration of one precision and degree."""
+        self._check(lib().dgp_set_launch(self._h, precision, int(p), int(cfg)), "dgp_set_launch")
 
     def kernel_ms(self, name: str) -> float:
         ms = C.c_float()

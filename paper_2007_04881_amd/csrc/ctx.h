@@ -25,6 +25,7 @@ struct dgp_ctx {
     int p_max = 0;
     int32_t *rows_by_p = nullptr;      // mixed degrees: element ids grouped by degree (stable)
     int64_t rows_off[dgp::kMaxP + 2] = {};  // group of degree p: rows_by_p[rows_off[p] .. rows_off[p + 1])
+    int32_t *rows_sub = nullptr;  // 2D: element ids by (degree, fan sub-triangle count), stable; same rows_off
     std::vector<void *> mesh_bufs;
     dgp::DevMesh dm{};
 
@@ -66,7 +67,9 @@ struct dgp_ctx {
     void *last_vals = nullptr, *last_rhs = nullptr;
 
     // register-budget variant of the 2D row kernel per [precision][degree] (dgp_autotune)
-    int8_t row_alt[2][dgp::kMaxP + 1] = {};
+    // 2D launch configuration per [FP64, FP32][degree]: bit 0 = the row kernel's
+    // register budget (one more wave per SIMD), bit 1 = rows in rows_sub order
+    int8_t row_cfg[2][dgp::kMaxP + 1] = {};
 
     bool timing = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};

@@ -44,6 +44,8 @@ static void free_mesh(dgp_ctx *c) {
     c->mesh_bufs.clear();
     if (c->rows_by_p) (void)hipFree(c->rows_by_p);
     c->rows_by_p = nullptr;
+    if (c->rows_sub) (void)hipFree(c->rows_sub);
+    c->rows_sub = nullptr;
     for (void *p : {(void *)c->row_ptr, (void *)c->col_idx, (void *)c->val_ptr, (void *)c->dof_ptr, c->work})
         if (p) (void)hipFree(p);
     c->row_ptr = c->val_ptr = c->dof_ptr = nullptr;
@@ -241,6 +243,24 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
             return fail(ctx, DGP_ENOMEM, "row groups");
         }
         HIPCHK(ctx, hipMemcpy(ctx->rows_by_p, rows.data(), sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice));
+    }
+    {
+        // the bins (p, n_sub) of Section 3.1's grouping refined by the number of
+        // fan sub-triangles n_sub = n_v - 2: element ids sorted by that key,
+        // stable in id (one of the two row orders dgp_autotune chooses from)
+        constexpr int NS = kMaxFaces2D;
+        std::vector<int64_t> bc((size_t)(kMaxP + 1) * NS + 1, 0);
+        auto key = [&](int64_t c) { return (int64_t)m->cell_p[c] * NS + (m->cell_ptr[c + 1] - m->cell_ptr[c] - 2); };
+        for (int64_t c = 0; c < N; ++c) bc[(size_t)key(c) + 1] += 1;
+        for (size_t k = 1; k < bc.size(); ++k) bc[k] += bc[k - 1];
+        for (int p = 0; p <= kMaxP + 1; ++p) ctx->rows_off[p] = bc[(size_t)p * NS];
+        std::vector<int32_t> rows((size_t)N);
+        for (int64_t c = 0; c < N; ++c) rows[(size_t)bc[(size_t)key(c)]++] = (int32_t)c;
+        if (hipMalloc(&ctx->rows_sub, sizeof(int32_t) * (size_t)N) != hipSuccess) {
+            free_mesh(ctx);
+            return fail(ctx, DGP_ENOMEM, "row bins");
+        }
+        HIPCHK(ctx, hipMemcpy(ctx->rows_sub, rows.data(), sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice));
     }
     ctx->has_mesh = true;
     return DGP_OK;
@@ -520,6 +540,17 @@ static dgp_status launch_assembly3d(dgp_ctx *ctx, const DevProblem &dp, int prec
     return DGP_OK;
 }
 
+// The rows of degree p for launch configuration cfg: id order (uniform degree:
+// all rows, no list) or, with bit 1, the (degree, sub-triangle count) order.
+static void row_range(const dgp_ctx *ctx, AsmArgs &a, int p, int cfg) {
+    const int64_t o = ctx->rows_off[p], n = ctx->rows_off[p + 1] - o;
+    if (cfg & 2)
+        a.rows = ctx->rows_sub + o;
+    else
+        a.rows = ctx->p_uniform > 0 ? nullptr : ctx->rows_by_p + o;
+    a.n_rows = (int32_t)n;
+}
+
 static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precision, int rule_mode, int values,
                                   int write_pattern, void *vals, void *rhs, hipStream_t st) {
     if (ctx->dim == 3) return launch_assembly3d(ctx, dp, precision, values, write_pattern, vals, rhs, st);
@@ -548,18 +579,13 @@ static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precis
     a.qr_w = ctx->qr_w;
     a.qr_ok = ctx->qr_ok;
     const int pi = precision == DGP_F32 ? 1 : 0;
-    if (ctx->p_uniform > 0) {
-        if (!launch_row2d(a, precision, ctx->p_uniform, false, ctx->row_alt[pi][ctx->p_uniform], st))
-            return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, ctx->p_uniform);
-    } else {
-        for (int p = 1; p <= kMaxP; ++p) {
-            const int64_t n = ctx->rows_off[p + 1] - ctx->rows_off[p];
-            if (n == 0) continue;
-            a.rows = ctx->rows_by_p + ctx->rows_off[p];
-            a.n_rows = (int32_t)n;
-            if (!launch_row2d(a, precision, p, true, ctx->row_alt[pi][p], st))
-                return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
-        }
+    for (int p = 1; p <= kMaxP; ++p) {
+        if (ctx->p_uniform > 0 && p != ctx->p_uniform) continue;
+        if (ctx->rows_off[p + 1] == ctx->rows_off[p]) continue;
+        const int cfg = ctx->row_cfg[pi][p];
+        row_range(ctx, a, p, cfg);
+        if (!launch_row2d(a, precision, p, ctx->p_uniform <= 0, cfg & 1, st))
+            return fail(ctx, DGP_EUNSUPPORTED, "no kernel for precision %d, p %d", precision, p);
     }
     return DGP_OK;
 }
@@ -705,16 +731,16 @@ dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice) {
             const bool present = ctx->p_uniform > 0 ? p == ctx->p_uniform : ctx->rows_off[p + 1] > ctx->rows_off[p];
             if (present) bins[nbins++] = p;
         }
-        // each variant of each bin gets an equal share of the budget (at least one launch)
-        const float share = (float)budget_ms / (float)(2 * (nbins > 0 ? nbins : 1));
+        // each configuration of each bin gets an equal share of the budget (at least one launch)
+        const float share = (float)budget_ms / (float)(kLaunchCfgs * (nbins > 0 ? nbins : 1));
         for (int b = 0; b < nbins; ++b) {
             const int p = bins[b];
             const bool mixed = ctx->p_uniform <= 0;
-            a.rows = mixed ? ctx->rows_by_p + ctx->rows_off[p] : nullptr;
-            a.n_rows = (int32_t)(mixed ? ctx->rows_off[p + 1] - ctx->rows_off[p] : ctx->n_cells);
             float best = 0.0f;
-            int best_alt = 0;
-            for (int alt = 0; alt < 2; ++alt) {
+            int best_cfg = 0;
+            for (int cfg = 0; cfg < kLaunchCfgs; ++cfg) {
+                const int alt = cfg & 1;
+                row_range(ctx, a, p, cfg);
                 // one warm launch, then as many timed launches as fit in the share
                 HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
                 launch_row2d(a, ctx->last_precision, p, mixed, alt, st);
@@ -731,18 +757,27 @@ dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice) {
                 float ms = 0.0f;
                 HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
                 ms /= (float)reps;
-                if (alt == 0 || ms < best) {
+                if (cfg == 0 || ms < best) {
                     best = ms;
-                    best_alt = alt;
+                    best_cfg = cfg;
                 }
             }
-            ctx->row_alt[pi][p] = (int8_t)best_alt;
+            ctx->row_cfg[pi][p] = (int8_t)best_cfg;
         }
         ctx->ev_pattern = ctx->ev_assemble = false;
     }
     if (choice)
         for (int q = 0; q < 2; ++q)
-            for (int p = 0; p <= kMaxP; ++p) choice[q * (kMaxP + 1) + p] = ctx->row_alt[q][p];
+            for (int p = 0; p <= kMaxP; ++p) choice[q * (kMaxP + 1) + p] = ctx->row_cfg[q][p];
+    return DGP_OK;
+}
+
+dgp_status dgp_set_launch(dgp_ctx *ctx, int precision, int p, int cfg) {
+    if (!ctx) return DGP_EINVAL;
+    if (precision != DGP_F64 && precision != DGP_F32) return fail(ctx, DGP_EINVAL, "precision %d", precision);
+    if (p < 1 || p > kMaxP) return fail(ctx, DGP_EUNSUPPORTED, "p = %d outside 1..%d", p, kMaxP);
+    if (cfg < 0 || cfg >= kLaunchCfgs) return fail(ctx, DGP_EINVAL, "launch configuration %d outside 0..%d", cfg, kLaunchCfgs - 1);
+    ctx->row_cfg[precision == DGP_F32 ? 1 : 0][p] = (int8_t)cfg;
     return DGP_OK;
 }
 

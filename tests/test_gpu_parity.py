@@ -207,10 +207,54 @@ def test_autotune_keeps_results(precision):
     torch.cuda.synchronize()
     v0, r0 = vals.clone(), rhs.clone()
     choice = ctx.autotune(50)
-    assert all(c in (0, 1) for row in choice for c in row)
+    assert all(c in (0, 1, 2, 3) for row in choice for c in row)
     vals.fill_(float("nan"))
     rhs.fill_(float("nan"))
     ctx.assemble(DAR, precision, vals, rhs)
     torch.cuda.synchronize()
     assert torch.equal(vals, v0) and torch.equal(rhs, r0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_launch_configurations(mixed, precision):
+    """Every 2D launch configuration (register budget x row order: id order or
+    the (degree, sub-triangle count) bins) gives bit-identical values and the
+    full path's pattern; configuration 0 is checked against the oracle."""
+    import torch
+    import paper_2007_04881_amd as D
+
+    m = voronoi_mesh(1500, 84, lloyd=0, p=2)  # raw seeds: 3 to 12 vertices per cell
+    if mixed:
+        m = m.with_degrees(np.random.default_rng(9).integers(1, 5, m.n_cells))
+    pat = oracle.pattern(m)
+    ctx = D.Context(0)
+    ctx.upload(m)
+    ctx.pattern()
+    vals, rhs = ctx.outputs(precision)
+    ref = None
+    for cfg in range(4):
+        print(f"[case] mixed={mixed} prec={precision} cfg={cfg}", flush=True)
+        for p in range(1, 5):
+            ctx.set_launch(precision, p, cfg)
+        vals.fill_(float("nan"))
+        rhs.fill_(float("nan"))
+        ctx.run(DAR, precision, vals, rhs)
+        rp, ci, vp, dp = ctx.pattern_tensors()
+        torch.cuda.synchronize()
+        assert np.array_equal(rp.cpu().numpy(), pat.row_ptr) and np.array_equal(ci.cpu().numpy(), pat.col_idx)
+        assert np.array_equal(vp.cpu().numpy(), pat.val_ptr) and np.array_equal(dp.cpu().numpy(), pat.dof_ptr)
+        if ref is None:
+            ref = vals.clone(), rhs.clone()
+            g = dict(vals=vals.double().cpu().numpy(), rhs=rhs.double().cpu().numpy())
+            ov, orhs = oracle.assemble(m, oracle_problem(DAR), pat=pat)
+            eb, er = block_errors(g, ov, orhs, pat)
+            assert eb <= TOL[precision] and er <= TOL[precision], (eb, er)
+        else:
+            assert torch.equal(vals, ref[0]) and torch.equal(rhs, ref[1])
+    with pytest.raises(D.DgpError):
+        ctx.set_launch(precision, 2, 4)
+    with pytest.raises(D.DgpError):
+        ctx.set_launch(precision, 5, 0)
     ctx.close()
