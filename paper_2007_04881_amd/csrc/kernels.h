@@ -10,8 +10,9 @@
 namespace dgp {
 
 // Geometry, edge neighbours and row sizes, then the scan of the tile sums (two launches).
-// scan = false: the tile sums are left for the assembly kernel to sum (see AsmArgs::tile_sum)
-void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st, bool scan = true);
+// scan = false: the tile sums are left for the assembly kernel to sum (see AsmArgs::tile_sum);
+// p_uniform > 0: the common degree of all cells (or -1)
+void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st, bool scan, int p_uniform);
 
 // One wave per element row: pattern (if a.write_pattern) and values of rows
 // a.rows[0 .. n_rows) (all rows in order if a.rows is null), all of degree p;

@@ -231,7 +231,7 @@ dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dg
     DevProblem neutral{};
     neutral.a0 = 1.0;
     neutral.c_sigma = 10.0;
-    launch_prep(ctx->dm, neutral, ctx->prep, st);
+    launch_prep(ctx->dm, neutral, ctx->prep, st, true, ctx->p_uniform);
     launch_cell_poly(ctx->dm, ctx->prep.geo, ctx->qr_feat, ctx->qr_mom, ctx->qr_area, ctx->qr_elig, st);
     HIPCHK(ctx, hipEventRecord(ev[1], st));
     if (init == DGP_INIT_NETWORK) {

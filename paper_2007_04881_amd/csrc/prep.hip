@@ -87,7 +87,8 @@ __device__ double max_a_points(const DevProblem &pr, const TrigCentre &tc, const
 
 }  // namespace
 
-__global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut out) {
+// p_uniform > 0: every cell has that degree (no neighbour degree is read)
+__global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut out, int p_uniform) {
     __shared__ int s_cnt[CPB][3];
     __shared__ double2 s_xy[CPB][kMaxFaces2D];  // each element's vertex loop
 
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
             out.nbr[s + f] = code[q];
             if (o >= 0 && o != c) {
                 nb[q] = o;
-                nbsz[q] = nb2d(m.cell_p[o]);
+                nbsz[q] = nb2d(p_uniform > 0 ? p_uniform : m.cell_p[o]);
             }
             vq[q] = m.cell_vtx[s + f];
             xq[q] = m.x[vq[q]];
@@ -349,9 +350,9 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int32_t *__restrict__ 
         for (int q = 0; q < 3; ++q) tile_off[3 * n_tiles + q] = sh[q][1023];
 }
 
-void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st, bool scan) {
+void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hipStream_t st, bool scan, int p_uniform) {
     const int n_tiles = (m.n_cells + kPrepTile - 1) / kPrepTile;
-    hipLaunchKernelGGL(k_prep, dim3(n_tiles), dim3(WG), 0, st, m, pr, out);
+    hipLaunchKernelGGL(k_prep, dim3(n_tiles), dim3(WG), 0, st, m, pr, out, p_uniform);
     if (scan) hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, out.tile_sum, n_tiles, out.tile_off);
 }
 

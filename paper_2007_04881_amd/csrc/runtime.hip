@@ -418,7 +418,7 @@ static void launch_prep_any(dgp_ctx *ctx, const DevProblem &dp, hipStream_t st, 
     if (ctx->dim == 3)
         launch_prep3d(ctx->dm, dp, ctx->prep3, st);
     else
-        launch_prep(ctx->dm, dp, ctx->prep, st, !inline_tiles(ctx, values));
+        launch_prep(ctx->dm, dp, ctx->prep, st, !inline_tiles(ctx, values), ctx->p_uniform);
 }
 
 dgp_status dgp_pattern(dgp_ctx *ctx, dgp_pattern_info *out) {

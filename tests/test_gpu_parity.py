@@ -87,6 +87,13 @@ def test_workload5_p3_full_size():
     _sampled_case(config_mesh(5), problem_params(5), 1)
 
 
+@pytest.mark.parametrize("n_cells", [32768, 32800])
+def test_tile_sums_at_the_inline_limit(n_cells):
+    # 1,024 tiles of 32 cells: the assembly adds up the tile sums before its
+    # tile itself (up to 16 loads per lane); 1,025 tiles: the scan kernel runs
+    _sampled_case(voronoi_mesh(n_cells, 85, lloyd=0, p=2), DAR, 1, n_sample=200)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_polynomial_data_and_full_path(precision):
     m = voronoi_mesh(333, 78, lloyd=2, p=2)
