@@ -286,7 +286,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build assembles on exactly one GPU (the method needs no communication; "
-              "the multi-GPU layout is described in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+              "the multi-GPU layout is described in the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
