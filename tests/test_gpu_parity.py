@@ -265,3 +265,42 @@ def test_launch_configurations(mixed, precision):
     with pytest.raises(D.DgpError):
         ctx.set_launch(precision, 5, 0)
     ctx.close()
+
+
+def test_back_to_back_steps():
+    """Steps issued back to back without synchronisation, with different data
+    and outputs and a graph replay between them, equal the same steps run one
+    at a time (the preparation outputs are reused by every step)."""
+    import torch
+    import paper_2007_04881_amd as D
+
+    m = voronoi_mesh(3000, 86, lloyd=1, p=2)
+    probs = [DAR, POISSON, POLY, dict(DAR, a1=0.25, c=2.0), DAR, POLY]
+    ref = []
+    solo = D.Context(0)
+    solo.upload(m)
+    solo.pattern()
+    for pr in probs:
+        v, r = solo.outputs(1)
+        solo.run(pr, 1, v, r)
+        torch.cuda.synchronize()
+        ref.append((v.clone(), r.clone()))
+    solo.close()
+    ctx = D.Context(0)
+    ctx.upload(m)
+    ctx.pattern()
+    outs = [ctx.outputs(1) for _ in probs]
+    for v, r in outs:
+        v.fill_(float("nan"))
+        r.fill_(float("nan"))
+    torch.cuda.synchronize()
+    ctx.graph_capture(0, probs[2], 1, *outs[2])
+    for k in (0, 1):
+        ctx.run(probs[k], 1, *outs[k])
+    ctx.graph_launch()
+    for k in (3, 4, 5):
+        ctx.run(probs[k], 1, *outs[k])
+    torch.cuda.synchronize()
+    for k, (v, r) in enumerate(outs):
+        assert torch.equal(v, ref[k][0]) and torch.equal(r, ref[k][1]), k
+    ctx.close()
