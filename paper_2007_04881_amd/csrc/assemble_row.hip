@@ -238,6 +238,86 @@ __device__ __forceinline__ void cross_lds(const AsmArgs &A, const RowCtx &R, con
     wave_sync();  // the table is rewritten by the next point set
 }
 
+// Cross blocks on the matrix cores (the p >= 3 kernels): one edge group at a
+// time, its FG lanes write 3 rows each of normalised test terms u_a(i) and of
+// the neighbour's trial terms s_a(j) (normalised, scaled by its box factor;
+// zero on lanes without a point) to LDS, and 3 FG / 4 steps of the 16 x 16 x 4
+// instruction form the n_b(p) x n_b(p') block, written from the accumulator
+// layout (mf_row).  Columns beyond the neighbour's n_b are not written.
+template <typename T, int P, int PN>
+__device__ __forceinline__ void cross_mf(const AsmArgs &A, const RowCtx &R, const Eval<T, P> &ev,
+                                         const PointCoef<T> &pc, double xin, double etan, double xsc, int base,
+                                         int d, int og, int gvoff, int fk, int nbo) {
+    using C = RowCfg<T, P, PN>;
+    constexpr int NB = C::NB, NBN = C::NBN, FG = C::FG, KR = 3 * FG;
+    static_assert(KR % 4 == 0 && NB <= 16 && NBN <= 16, "one 16 x 16 tile per cross block");
+    T *U = static_cast<T *>(R.xs), *S = U + KR * 16;
+    const int lane = R.lane;
+    // this lane's trial terms (computed once, stored when its group's turn comes)
+    T sv[3][NBN];
+    {
+        T Lx[PN + 1], dLx[PN + 1], Ly[PN + 1], dLy[PN + 1];
+        legendre<T, PN>(T(xin), Lx, dLx);
+        legendre<T, PN>(T(etan), Ly, dLy);
+#pragma unroll
+        for (int a = 1; a <= PN; ++a) {
+            Lx[a] *= T(kSqrt2a1[a]);
+            dLx[a] *= T(kSqrt2a1[a]);
+            Ly[a] *= T(kSqrt2a1[a]);
+            dLy[a] *= T(kSqrt2a1[a]);
+        }
+        const T xs_ = T(xsc);
+        const T sb0 = -pc.b0 * xs_, sb1 = -pc.b1 * xs_, sx0 = pc.x0 * xs_, sx1 = pc.x1 * xs_, sc2 = -pc.c2 * xs_;
+#pragma unroll
+        for (int j = 0; j < NBN; ++j) {
+            const T vj = Lx[exp_a(j)] * Ly[exp_b(j)];
+            const T gj0 = dLx[exp_a(j)] * Ly[exp_b(j)], gj1 = Lx[exp_a(j)] * dLy[exp_b(j)];
+            sv[0][j] = sb0 * vj;
+            sv[1][j] = sb1 * vj;
+            sv[2][j] = fmat(sx0, gj0, fmat(sx1, gj1, sc2 * vj));
+        }
+    }
+    const int gfirst = base > R.QF0 ? (base - R.QF0) / FG : 0;
+    const int glast = min(R.ng, (base + 64 - R.QF0) / FG);
+    T *__restrict__ vals = static_cast<T *>(A.vals);
+    for (int g = gfirst; g < glast; ++g) {
+        const int ql = R.QF0 + g * FG - base;  // the group's first lane (uniform)
+        const int oge = __builtin_amdgcn_readlane(og, ql), fke = __builtin_amdgcn_readlane(fk, ql);
+        if (oge < 0 || fke < 0) continue;
+        if (lane >= ql && lane < ql + FG) {
+            const int k0 = 3 * (lane - ql);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                U[(k0 + 0) * 16 + i] = ev.g0[i] * T(kNorm[i]);
+                U[(k0 + 1) * 16 + i] = ev.g1[i] * T(kNorm[i]);
+                U[(k0 + 2) * 16 + i] = ev.v[i] * T(kNorm[i]);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int j = 0; j < NBN; ++j) S[(k0 + a) * 16 + j] = sv[a][j];
+        }
+        wave_sync();
+        MfAcc<T> acc = {T(0), T(0), T(0), T(0)};
+        const int r4 = lane >> 4, c = lane & 15;
+#pragma unroll
+        for (int s = 0; s < KR / 4; ++s) acc = mfma16(U[(4 * s + r4) * 16 + c], S[(4 * s + r4) * 16 + c], acc);
+        wave_sync();  // the next group rewrites the table
+        const int nbog = __builtin_amdgcn_readlane(nbo, ql), gvo = __builtin_amdgcn_readlane(gvoff, ql);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = mf_row<T>(lane, r);
+            if (i < NB && c < nbog) {
+                T *dst = vals + R.pre_v + gvo + i * nbog + c;
+                if (d == 0)
+                    *dst = acc[r];
+                else
+                    *dst += acc[r];
+            }
+        }
+    }
+}
+
 template <typename T, int P, int PN, bool MX, bool ADV, int SL>
 __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
     using C = RowCfg<T, P, PN>;
@@ -421,6 +501,8 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             }
             if constexpr (C::XL) {
                 if (pass_has_edges) cross_lds<T, P, PN>(A, R, ev, pc, xin, etan, xsc, base, d, og, gvoff, fk);
+            } else if constexpr (C::MF) {
+                if (pass_has_edges) cross_mf<T, P, PN>(A, R, ev, pc, xin, etan, xsc, base, d, og, gvoff, fk, nbo);
             } else if (pass_has_edges) {
                 // cross block, one column at a time: the group's lanes sum the column
                 // (butterfly inside the group) and lane gq writes the entries i = gq mod FG
