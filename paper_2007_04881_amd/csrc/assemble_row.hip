@@ -75,6 +75,14 @@ struct RowCfg {
     // cross blocks through a per-wave LDS table (XL) instead of per-column group sums
     static constexpr bool XL = sizeof(T) == 4 && P <= 2 && PN <= 2;
     static constexpr int XW = 3 * (NB + NBN);  // table row per lane: test terms, then trial terms
+    // CM: cross blocks on the matrix cores (p >= 3, and the FP32 mixed-degree
+    // kernels, whose neighbours may have larger blocks than the row's own; in
+    // FP64 the staged trial terms cost those kernels a wave per SIMD: slower)
+    static constexpr bool CM = !XL && (P >= 3 || (PN > P && sizeof(T) == 4));
+    static constexpr int CMW = 2 * 3 * FG * 16;  // its table per wave (T elements)
+    // one LDS region per wave serves every table (their phases are separated by wave barriers)
+    static constexpr int LW0 = XL ? 64 * XW : 0, LW1 = MF ? MFW : 0, LW2 = CM ? CMW : 0;
+    static constexpr int LW = LW0 > LW1 ? (LW0 > LW2 ? LW0 : LW2) : (LW1 > LW2 ? LW1 : LW2);
 };
 
 // sqrt(2a + 1): the normalisation of the one-dimensional Legendre factor of degree a
@@ -238,7 +246,7 @@ __device__ __forceinline__ void cross_lds(const AsmArgs &A, const RowCtx &R, con
     wave_sync();  // the table is rewritten by the next point set
 }
 
-// Cross blocks on the matrix cores (the p >= 3 kernels): one edge group at a
+// Cross blocks on the matrix cores (the p >= 3 and mixed-degree kernels): one edge group at a
 // time, its FG lanes write 3 rows each of normalised test terms u_a(i) and of
 // the neighbour's trial terms s_a(j) (normalised, scaled by its box factor;
 // zero on lanes without a point) to LDS, and 3 FG / 4 steps of the 16 x 16 x 4
@@ -501,7 +509,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             }
             if constexpr (C::XL) {
                 if (pass_has_edges) cross_lds<T, P, PN>(A, R, ev, pc, xin, etan, xsc, base, d, og, gvoff, fk);
-            } else if constexpr (C::MF) {
+            } else if constexpr (C::CM) {
                 if (pass_has_edges) cross_mf<T, P, PN>(A, R, ev, pc, xin, etan, xsc, base, d, og, gvoff, fk, nbo);
             } else if (pass_has_edges) {
                 // cross block, one column at a time: the group's lanes sum the column
@@ -714,8 +722,8 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     R.dvoff = dvoff;
     R.maxdup = max(maxdup, 1);
     R.ng = ng;
-    __shared__ T xlds[C::XL ? 4 * 64 * C::XW : C::MF ? 4 * C::MFW : 1];
-    R.xs = C::XL ? xlds + (threadIdx.x >> 6) * 64 * C::XW : C::MF ? xlds + (threadIdx.x >> 6) * C::MFW : nullptr;
+    __shared__ T xlds[C::LW > 0 ? 4 * C::LW : 1];
+    R.xs = C::LW > 0 ? xlds + (threadIdx.x >> 6) * C::LW : nullptr;
     R.gmask = gmask;
     {
         // lane g gets the position of the g-th set bit of gmask: a forward
