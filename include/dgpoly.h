@@ -43,7 +43,8 @@ extern "C" {
 typedef int32_t dgp_status;
 #define DGP_OK 0
 #define DGP_EINVAL (-1)       /* null pointer, size mismatch, bad enum */
-#define DGP_EMESH (-2)        /* malformed mesh: face not adjacent to its cells, bad ids, < 3 vertices */
+#define DGP_EMESH (-2)        /* malformed mesh: face not adjacent to its cells, bad ids, < 3 vertices,
+                                 clockwise or zero-area polygon, zero-volume tetrahedron */
 #define DGP_EUNSUPPORTED (-3) /* degree or dimension outside what the kernels are built for */
 #define DGP_ENOMEM (-4)       /* device allocation failed */
 #define DGP_EDEVICE (-5)      /* any HIP runtime error */
@@ -129,9 +130,18 @@ dgp_status dgp_set_stream(dgp_ctx *ctx, void *hip_stream);
 /* Text of the last failure on this context (static storage inside ctx). */
 const char *dgp_last_error(const dgp_ctx *ctx);
 
-/* Validate the mesh on the host (ids in range, every face listed by its cells,
- * loops of >= 3 vertices, degrees supported) and copy it to the device.
- * Synchronous.  Invalidates any previous pattern. */
+/* The host checks of dgp_mesh_upload, without a context or a device: ids in
+ * range, every face listed by the cells it bounds (2D: as the edge between
+ * consecutive loop vertices), loops of >= 3 vertices running counter-clockwise
+ * around a positive area (twice the signed area > 1e-13 times the squared
+ * diagonal of the cell's box), 3D tetrahedra of nonzero volume, supported
+ * degrees and sizes.  Returns DGP_EMESH, DGP_EINVAL or DGP_EUNSUPPORTED with
+ * the reason in msg[0 .. msg_len) (msg may be NULL).  No HIP call. */
+dgp_status dgp_mesh_check(const dgp_mesh_desc *mesh, char *msg, size_t msg_len);
+
+/* Validate the mesh on the host (as dgp_mesh_check; nothing reaches the device
+ * on failure) and copy it to the device.  Synchronous.  Invalidates any
+ * previous pattern. */
 dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *mesh);
 
 /* Block sparsity pattern on the device (Section 3.4): row r = sorted unique

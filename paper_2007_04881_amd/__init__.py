@@ -66,7 +66,7 @@ class TrainStats(C.Structure):
     _fields_ = [("loss_first", C.c_float), ("loss_last", C.c_float), ("ms", C.c_double), ("steps", C.c_int64)]
 
 
-EXPORTS = ["dgp_create", "dgp_destroy", "dgp_set_stream", "dgp_last_error", "dgp_mesh_upload", "dgp_pattern",
+EXPORTS = ["dgp_create", "dgp_destroy", "dgp_set_stream", "dgp_last_error", "dgp_mesh_check", "dgp_mesh_upload", "dgp_pattern",
            "dgp_pattern_copy", "dgp_assemble", "dgp_run", "dgp_graph_capture", "dgp_graph_launch",
            "dgp_set_timing", "dgp_kernel_ms", "dgp_time_kernels", "dgp_autotune", "dgp_set_launch", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
            "dgp_qrule_cell_data", "dgp_train_polygons", "dgp_mlp_forward", "dgp_mlp_loss_grad", "dgp_adam_step",
@@ -91,6 +91,7 @@ def lib():
             getattr(L, name).argtypes = [C.c_void_p]
         L.dgp_last_error.argtypes = [C.c_void_p]
         L.dgp_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+        L.dgp_mesh_check.argtypes = [C.POINTER(MeshDesc), C.c_char_p, C.c_size_t]
         L.dgp_mesh_upload.argtypes = [C.c_void_p, C.POINTER(MeshDesc)]
         L.dgp_pattern.argtypes = [C.c_void_p, C.POINTER(PatternInfo)]
         L.dgp_pattern_copy.argtypes = [C.c_void_p] + [C.c_void_p] * 4
@@ -145,6 +146,30 @@ def _torch_stream(stream):
     return stream.cuda_stream
 
 
+def mesh_desc(mesh):
+    """dgp_mesh_desc of a mesh (host arrays), and the arrays it points into (keep them alive)."""
+    arrs = {k: np.ascontiguousarray(v) for k, v in mesh.arrays().items()}
+    d = MeshDesc()
+    d.dim = mesh.dim
+    d.n_vertices = mesh.n_vertices
+    d.x, d.y, d.z = _ptr(arrs["x"]), _ptr(arrs["y"]), _ptr(arrs["z"])
+    d.n_cells = mesh.n_cells
+    d.cell_ptr, d.cell_vtx, d.cell_p = _ptr(arrs["cell_ptr"]), _ptr(arrs["cell_vtx"]), _ptr(arrs["cell_p"])
+    d.cell_face_ptr, d.cell_face = _ptr(arrs["cell_face_ptr"]), _ptr(arrs["cell_face"])
+    d.n_faces = mesh.n_faces
+    d.face_vtx, d.face_cell, d.face_bc = _ptr(arrs["face_vtx"]), _ptr(arrs["face_cell"]), _ptr(arrs["face_bc"])
+    d.face_opp = _ptr(arrs.get("face_opp"))
+    return d, arrs
+
+
+def mesh_check(mesh):
+    """The library's host checks of a mesh (dgp_mesh_check, no device): (status, message)."""
+    d, arrs = mesh_desc(mesh)
+    buf = C.create_string_buffer(512)
+    st = lib().dgp_mesh_check(C.byref(d), buf, len(buf))
+    return st, buf.value.decode()
+
+
 class Context:
     """One device, one HIP stream; owns the device mesh, geometry and pattern."""
 
@@ -177,17 +202,7 @@ class Context:
         self._check(lib().dgp_set_stream(self._h, C.c_void_p(_torch_stream(stream))), "dgp_set_stream")
 
     def upload(self, mesh):
-        arrs = {k: np.ascontiguousarray(v) for k, v in mesh.arrays().items()}
-        d = MeshDesc()
-        d.dim = mesh.dim
-        d.n_vertices = mesh.n_vertices
-        d.x, d.y, d.z = _ptr(arrs["x"]), _ptr(arrs["y"]), _ptr(arrs["z"])
-        d.n_cells = mesh.n_cells
-        d.cell_ptr, d.cell_vtx, d.cell_p = _ptr(arrs["cell_ptr"]), _ptr(arrs["cell_vtx"]), _ptr(arrs["cell_p"])
-        d.cell_face_ptr, d.cell_face = _ptr(arrs["cell_face_ptr"]), _ptr(arrs["cell_face"])
-        d.n_faces = mesh.n_faces
-        d.face_vtx, d.face_cell, d.face_bc = _ptr(arrs["face_vtx"]), _ptr(arrs["face_cell"]), _ptr(arrs["face_bc"])
-        d.face_opp = _ptr(arrs.get("face_opp"))
+        d, arrs = mesh_desc(mesh)
         self._check(lib().dgp_mesh_upload(self._h, C.byref(d)), "dgp_mesh_upload")
         self.info = None
 
@@ -217,13 +232,21 @@ class Context:
         dev = torch.device("cuda", self.device)
         return torch.empty(i.n_vals, dtype=dt, device=dev), torch.empty(i.n_dofs, dtype=dt, device=dev)
 
-    @staticmethod
-    def _tensors_ok(vals, rhs, precision):
+    def _tensors_ok(self, vals, rhs, precision):
+        """Output tensors of the right type, device and size.  The library keeps
+        their addresses for graph replays and re-timed launches, so the context
+        holds a reference to the last pair until the next call replaces it."""
         import torch
         dt = torch.float32 if precision == F32 else torch.float64
         for t in (vals, rhs):
             if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
                 raise ValueError(f"outputs must be contiguous {dt} device tensors")
+            if t.device.index != self.device:
+                raise ValueError(f"outputs on {t.device}, context on cuda:{self.device}")
+        i = self.info or self.pattern()
+        if vals.numel() < i.n_vals or rhs.numel() < i.n_dofs:
+            raise ValueError(f"outputs too small: vals {vals.numel()} < {i.n_vals} or rhs {rhs.numel()} < {i.n_dofs}")
+        self._keep = (vals, rhs)
 
     def assemble(self, problem: dict, precision, vals, rhs, rule_mode=RULE_PLAIN):
         self._tensors_ok(vals, rhs, precision)

@@ -2,6 +2,7 @@
 // validation, device buffers, kernel launches, graph capture and timing.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -119,11 +120,10 @@ const char *dgp_last_error(const dgp_ctx *ctx) { return ctx ? ctx->err : "null c
 
 static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m);
 
-dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
-    if (!ctx || !m) return DGP_EINVAL;
-    HIPCHK(ctx, hipSetDevice(ctx->device));
-    if (m->dim == 3) return upload3d(ctx, m);
-    if (m->dim != 2) return fail(ctx, DGP_EUNSUPPORTED, "dim %d", m->dim);
+static dgp_status validate3d(dgp_ctx *ctx, const dgp_mesh_desc *m, int *pmin_out, int *pmax_out);
+
+// Host checks of a 2D mesh (no device work); err text goes to ctx->err.
+static dgp_status validate2d(dgp_ctx *ctx, const dgp_mesh_desc *m, int *pmin_out, int *pmax_out) {
     if (m->n_cells <= 0 || m->n_vertices <= 0 || m->n_faces <= 0)
         return fail(ctx, DGP_EINVAL, "empty mesh (cells %lld, vertices %lld, faces %lld)", (long long)m->n_cells,
                     (long long)m->n_vertices, (long long)m->n_faces);
@@ -160,8 +160,26 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
                 return fail(ctx, DGP_EMESH, "face %d does not match edge %lld of cell %lld", f, (long long)(k - s),
                             (long long)c);
         }
+        // the loop must run counter-clockwise around a cell of positive area: the
+        // kernels take outward normals and fan weights from that orientation.
+        // Twice the signed area (shoelace about the first vertex) against the
+        // square of the box extent, so that the test does not depend on scale.
+        const double x0 = m->x[m->cell_vtx[s]], y0 = m->y[m->cell_vtx[s]];
+        double a2 = 0.0, lx = x0, hx = x0, ly = y0, hy = y0;
+        for (int64_t k = s; k < e; ++k) {
+            const int32_t v = m->cell_vtx[k], w = m->cell_vtx[k + 1 < e ? k + 1 : s];
+            const double xv = m->x[v], yv = m->y[v];
+            a2 += (xv - x0) * (m->y[w] - y0) - (m->x[w] - x0) * (yv - y0);
+            lx = xv < lx ? xv : lx;
+            hx = xv > hx ? xv : hx;
+            ly = yv < ly ? yv : ly;
+            hy = yv > hy ? yv : hy;
+        }
+        const double ext2 = (hx - lx) * (hx - lx) + (hy - ly) * (hy - ly);
+        if (!(a2 > 1e-13 * ext2))
+            return fail(ctx, DGP_EMESH, "cell %lld: %s vertex loop (twice the signed area %.3e)", (long long)c,
+                        a2 < 0.0 ? "clockwise" : "zero-area", a2);
     }
-    int64_t nnz_v = m->cell_ptr[N];
     for (int64_t f = 0; f < F; ++f) {
         int32_t l = m->face_cell[2 * f], r = m->face_cell[2 * f + 1];
         int8_t bc = m->face_bc[f];
@@ -172,6 +190,33 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
         if (m->face_vtx[2 * f] >= m->face_vtx[2 * f + 1])
             return fail(ctx, DGP_EMESH, "face %lld: vertices not in canonical (ascending) order", (long long)f);
     }
+    *pmin_out = pmin;
+    *pmax_out = pmax;
+    return DGP_OK;
+}
+
+dgp_status dgp_mesh_check(const dgp_mesh_desc *m, char *msg, size_t msg_len) {
+    if (msg && msg_len) msg[0] = 0;
+    if (!m) return DGP_EINVAL;
+    dgp_ctx tmp;  // carries the message only; no device state is touched
+    int pmin = 0, pmax = 0;
+    dgp_status st = m->dim == 3   ? validate3d(&tmp, m, &pmin, &pmax)
+                    : m->dim == 2 ? validate2d(&tmp, m, &pmin, &pmax)
+                                  : fail(&tmp, DGP_EUNSUPPORTED, "dim %d", m->dim);
+    if (msg && msg_len) snprintf(msg, msg_len, "%s", tmp.err);
+    return st;
+}
+
+dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
+    if (!ctx || !m) return DGP_EINVAL;
+    if (m->dim == 3) return upload3d(ctx, m);
+    if (m->dim != 2) return fail(ctx, DGP_EUNSUPPORTED, "dim %d", m->dim);
+    int pmin = 0, pmax = 0;
+    dgp_status vst = validate2d(ctx, m, &pmin, &pmax);
+    if (vst != DGP_OK) return vst;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int64_t N = m->n_cells, F = m->n_faces, V = m->n_vertices;
+    const int64_t nnz_v = m->cell_ptr[N];
     free_mesh(ctx);
     ctx->dim = 2;
     ctx->n_cell_face = nnz_v;
@@ -268,7 +313,7 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
 
 // Polyhedral mesh: cells are unions of tetrahedra (4 ids each), faces are
 // triangles with the opposite vertex of the left cell's tetrahedron.
-static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
+static dgp_status validate3d(dgp_ctx *ctx, const dgp_mesh_desc *m, int *pmin_out, int *pmax_out) {
     if (m->n_cells <= 0 || m->n_vertices <= 0 || m->n_faces <= 0)
         return fail(ctx, DGP_EINVAL, "empty mesh (cells %lld, vertices %lld, faces %lld)", (long long)m->n_cells,
                     (long long)m->n_vertices, (long long)m->n_faces);
@@ -288,6 +333,33 @@ static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
         for (int64_t k = s; k < e; ++k)
             if (m->cell_vtx[k] < 0 || m->cell_vtx[k] >= V)
                 return fail(ctx, DGP_EMESH, "cell %lld: vertex id %d out of range", (long long)c, m->cell_vtx[k]);
+        // every tetrahedron must have positive volume (either orientation: the
+        // volume weights use |det|); relative to the cube of its longest edge
+        for (int64_t k = s; k < e; k += 4) {
+            double v[4][3], l2 = 0.0;
+            for (int j = 0; j < 4; ++j) {
+                const int32_t id = m->cell_vtx[k + j];
+                v[j][0] = m->x[id];
+                v[j][1] = m->y[id];
+                v[j][2] = m->z[id];
+            }
+            double d[3][3];
+            for (int j = 0; j < 3; ++j)
+                for (int q = 0; q < 3; ++q) d[j][q] = v[j + 1][q] - v[0][q];
+            for (int j = 0; j < 4; ++j)
+                for (int i = j + 1; i < 4; ++i) {
+                    const double e2 = (v[i][0] - v[j][0]) * (v[i][0] - v[j][0]) +
+                                      (v[i][1] - v[j][1]) * (v[i][1] - v[j][1]) +
+                                      (v[i][2] - v[j][2]) * (v[i][2] - v[j][2]);
+                    l2 = e2 > l2 ? e2 : l2;
+                }
+            const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                               d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                               d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+            if (!(fabs(det) > 1e-13 * l2 * sqrt(l2)))
+                return fail(ctx, DGP_EMESH, "cell %lld: tetrahedron %lld has zero volume", (long long)c,
+                            (long long)((k - s) / 4));
+        }
         const int p = m->cell_p[c];
         if (p < 1 || p > kMaxP3D) return fail(ctx, DGP_EUNSUPPORTED, "3D cell %lld has degree %d (1..%d)", (long long)c, p, kMaxP3D);
         pmin = p < pmin ? p : pmin;
@@ -318,6 +390,17 @@ static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
             if (v < 0 || v >= V || v == o) return fail(ctx, DGP_EMESH, "face %lld: bad vertex %d", (long long)f, v);
         }
     }
+    *pmin_out = pmin;
+    *pmax_out = pmax;
+    return DGP_OK;
+}
+
+static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
+    int pmin = 0, pmax = 0;
+    dgp_status vst = validate3d(ctx, m, &pmin, &pmax);
+    if (vst != DGP_OK) return vst;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int64_t N = m->n_cells, F = m->n_faces, V = m->n_vertices;
     free_mesh(ctx);
     const int64_t n_cv = m->cell_ptr[N], n_cf = m->cell_face_ptr[N];
     ctx->dim = 3;

@@ -38,30 +38,45 @@ def check_pattern(g, pat):
     assert g["info"][1:] == (pat.nnzb, pat.n_vals, pat.n_dofs)
 
 
-def block_errors(g, vals_ref, rhs_ref, pat, rows=None):
-    """Largest per-block relative Frobenius error of the matrix and per-row of the rhs."""
-    rows = range(len(pat.row_ptr) - 1) if rows is None else rows
-    worst_b = 0.0
-    worst_r = 0.0
-    # with sampled rows the oracle leaves the other rows NaN: scale by the sampled ones
-    rhs_scale = max(np.abs(rhs_ref[pat.dof_ptr[r]:pat.dof_ptr[r + 1]]).max() for r in rows)
-    for r in rows:
-        for k in range(pat.row_ptr[r], pat.row_ptr[r + 1]):
-            sl = slice(pat.val_ptr[k], pat.val_ptr[k + 1])
-            ref = vals_ref[sl]
-            nrm = np.linalg.norm(ref)
-            err = np.linalg.norm(g["vals"][sl] - ref)
-            assert not np.isnan(err), f"block {k} of row {r} is NaN"
-            worst_b = max(worst_b, err / nrm if nrm > 0 else err)
-        sl = slice(pat.dof_ptr[r], pat.dof_ptr[r + 1])
-        ref = rhs_ref[sl]
-        assert not np.isnan(ref).any(), f"oracle load of row {r} missing"
-        nrm = np.linalg.norm(ref)
-        err = np.linalg.norm(g["rhs"][sl] - ref)
-        assert not np.isnan(err), f"load of row {r} is NaN"
-        # a row whose load vanishes (g_D = 0, f ~ 0) is compared in absolute terms
-        worst_r = max(worst_r, err / nrm if nrm > 1e-10 * rhs_scale else err / rhs_scale)
+def block_errors(g, vals_ref, rhs_ref, pat, rows=None, where=None):
+    """Largest per-block relative Frobenius error of the matrix and per-row of the
+    right-hand side (numpy segment sums over val_ptr / dof_ptr).  ``rows``
+    restricts the check to those block rows (the oracle leaves the others NaN).
+    ``where`` (a dict) receives the row and block of the worst matrix error."""
+    n_rows = len(pat.row_ptr) - 1
+    rows = np.arange(n_rows) if rows is None else np.unique(np.asarray(rows, dtype=np.int64))
+    # blocks of the selected rows
+    cnt = pat.row_ptr[rows + 1] - pat.row_ptr[rows]
+    blk = np.repeat(pat.row_ptr[rows], cnt) + (np.arange(cnt.sum()) - np.repeat(np.cumsum(cnt) - cnt, cnt))
+    brow = np.repeat(rows, cnt)
+    b0, b1 = pat.val_ptr[blk], pat.val_ptr[blk + 1]
+    worst_b = _segment_worst(g["vals"], vals_ref, b0, b1, what="block", where=where, ids=(brow, blk))
+    d0, d1 = pat.dof_ptr[rows], pat.dof_ptr[rows + 1]
+    worst_r = _segment_worst(g["rhs"], rhs_ref, d0, d1, what="load", rows_for_abs=True)
     return worst_b, worst_r
+
+
+def _segment_worst(got, ref, s0, s1, what, where=None, ids=None, rows_for_abs=False):
+    lens = s1 - s0
+    assert (lens > 0).all()
+    idx = np.repeat(s0, lens) + (np.arange(lens.sum()) - np.repeat(np.cumsum(lens) - lens, lens))
+    r = ref[idx]
+    d = got[idx] - r
+    assert not np.isnan(r).any(), f"oracle {what} missing"
+    assert not np.isnan(d).any(), f"{what} is NaN"
+    starts = np.cumsum(lens) - lens
+    nrm = np.sqrt(np.add.reduceat(r * r, starts))
+    err = np.sqrt(np.add.reduceat(d * d, starts))
+    if rows_for_abs:
+        # a row whose load vanishes (g_D = 0, f ~ 0) is compared in absolute terms
+        scale = np.abs(r).max()
+        rel = np.where(nrm > 1e-10 * scale, err / np.where(nrm > 0, nrm, 1.0), err / scale)
+    else:
+        rel = np.where(nrm > 0, err / np.where(nrm > 0, nrm, 1.0), err)
+    k = int(np.argmax(rel))
+    if where is not None and ids is not None:
+        where.update(row=int(ids[0][k]), block=int(ids[1][k]), err=float(rel[k]))
+    return float(rel[k])
 
 
 def oracle_problem(params):

@@ -1,10 +1,13 @@
 """CPU checks of the C-ABI library: it loads, exports every function the header
 declares, and the binding mirrors the header's structs.  No device calls."""
 
+import copy
 import ctypes as C
 import os
 import re
 import subprocess
+
+import numpy as np
 
 import paper_2007_04881_amd as D
 
@@ -50,3 +53,45 @@ def test_struct_layouts_match_header(tmp_path):
 def test_library_is_built_for_gfx950():
     data = open(D.LIB_PATH, "rb").read()
     assert b"gfx950" in data
+
+
+def _reverse_loop(m, c):
+    """Copy of a 2D mesh with cell c's vertex loop reversed (clockwise), faces kept consistent."""
+    m2 = copy.deepcopy(m)
+    s, e = int(m.cell_ptr[c]), int(m.cell_ptr[c + 1])
+    n = e - s
+    loop = m.cell_vtx[s:e].copy()
+    faces = m.cell_face[s:e].copy()
+    # reversed loop [v0, v_{n-1}, ..., v1]: its edge k joins old vertices n-k and n-k-1
+    m2.cell_vtx[s:e] = np.concatenate([loop[:1], loop[1:][::-1]])
+    m2.cell_face[s:e] = [faces[(n - 1 - k) % n] for k in range(n)]
+    return m2
+
+
+def test_mesh_check_rejects_clockwise_and_degenerate_cells():
+    """dgp_mesh_check (host only): a valid mesh passes; a clockwise loop, a
+    zero-area polygon and a zero-volume tetrahedron fail with DGP_EMESH before
+    anything reaches a device."""
+    from meshgen import cube_cells, voronoi_mesh
+    from meshgen.mesh import Mesh
+
+    m = voronoi_mesh(40, 5, lloyd=1, p=2)
+    assert D.mesh_check(m) == (0, "")
+    st, msg = D.mesh_check(_reverse_loop(m, 7))
+    assert st == -2 and "clockwise" in msg and "cell 7" in msg, msg
+    # a triangle whose three vertices lie on one line
+    tri = Mesh(dim=2, x=np.array([0.0, 1.0, 2.0]), y=np.array([0.0, 0.0, 0.0]), z=np.zeros(0),
+               cell_ptr=np.array([0, 3], np.int64), cell_vtx=np.array([0, 1, 2], np.int32),
+               cell_p=np.array([1], np.int8), cell_face_ptr=np.array([0, 3], np.int64),
+               cell_face=np.array([0, 1, 2], np.int32), face_vtx=np.array([0, 1, 1, 2, 0, 2], np.int32),
+               face_cell=np.array([0, -1, 0, -1, 0, -1], np.int32), face_bc=np.array([1, 1, 1], np.int8))
+    st, msg = D.mesh_check(tri)
+    assert st == -2 and "zero-area" in msg, msg
+    good = cube_cells(2, p=2)
+    assert D.mesh_check(good)[0] == 0
+    flat = copy.deepcopy(good)
+    flat.z = np.zeros_like(good.z)
+    st, msg = D.mesh_check(flat)
+    assert st == -2 and "zero volume" in msg, msg
+    # degrees the kernels are not built for
+    assert D.mesh_check(m.with_degrees(5))[0] == -3

@@ -32,8 +32,9 @@ def _case(mesh, params, precision, rows=None):
     g = gpu_assemble(mesh, params, precision)
     check_pattern(g, pat)
     vals, rhs = oracle.assemble(mesh, oracle_problem(params), rows=rows, pat=pat)
-    eb, er = block_errors(g, vals, rhs, pat, rows=rows)
-    print(f"       worst block {eb:.3e}  worst rhs row {er:.3e}", flush=True)
+    where = {}
+    eb, er = block_errors(g, vals, rhs, pat, rows=rows, where=where)
+    print(f"       worst block {eb:.3e} (row {where['row']})  worst rhs row {er:.3e}", flush=True)
     assert eb <= TOL[precision], eb
     assert er <= TOL[precision], er
     return g
@@ -56,6 +57,12 @@ def test_mixed_degrees_3d(precision):
     m = agglomerated_cube(8, 70, 2026, p=1)
     m = m.with_degrees(np.random.default_rng(5).integers(1, 3, m.n_cells))
     _case(m, DAR3, precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pure_advection_3d(precision):
+    """a = 0: advection, reaction and upwind faces only (sigma = 0)."""
+    _case(agglomerated_cube(8, 70, 2032, p=2), dict(ADV3, a0=0.0, c=0.7), precision)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -128,11 +135,21 @@ def test_3d_graph_replay_deterministic():
 @pytest.mark.parametrize("precision", [1, 0])
 def test_workload4_full_size_sampled(precision):
     """128^3 cubes, 12.6M Kuhn tetrahedra in 32,768 polyhedra, p = 2: full
-    pattern, values of 48 sampled rows (first, last, and spread)."""
+    pattern, values of 2,049 rows (every 16th row, and the last)."""
     m = config_mesh(4)
-    rng = np.random.default_rng(11)
-    rows = np.unique(np.concatenate([[0, m.n_cells - 1], rng.integers(0, m.n_cells, 46)]))
+    rows = np.unique(np.concatenate([np.arange(0, m.n_cells, 16), [m.n_cells - 1]]))
     _case(m, problem_params(4), precision, rows=rows)
+
+
+@pytest.mark.parametrize("params", [DAR3, ADV3], ids=["dar", "adv"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cells_near_their_centre(params, precision):
+    """16^3 cubes of 6 tetrahedra each: every cell fits within the radius where
+    the kernels take sin/cos of the manufactured data by angle addition from
+    the box centre (pi times half the box diagonal <= 0.2), so the short series
+    of the load, with and without advection, are compared in full."""
+    m = cube_cells(16, p=2)
+    _case(m, params, precision)
 
 
 def test_3d_error_paths():

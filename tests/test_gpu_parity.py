@@ -28,8 +28,9 @@ def _case(mesh, params, precision, full_path=False):
     g = gpu_assemble(mesh, params, precision, full_path)
     check_pattern(g, pat)
     vals, rhs = oracle.assemble(mesh, oracle_problem(params), pat=pat)
-    eb, er = block_errors(g, vals, rhs, pat)
-    print(f"       worst block {eb:.3e}  worst rhs row {er:.3e}", flush=True)
+    where = {}
+    eb, er = block_errors(g, vals, rhs, pat, where=where)
+    print(f"       worst block {eb:.3e} (row {where['row']})  worst rhs row {er:.3e}", flush=True)
     assert eb <= TOL[precision], eb
     assert er <= TOL[precision], er
     return g
@@ -62,42 +63,56 @@ def test_mixed_degrees(precision):
     _case(m, POLY, precision, full_path=True)
 
 
-def _sampled_case(mesh, params, precision, n_sample=400):
-    """Full-size run in the benchmark's launch configuration; the pattern is
-    compared in full, values on sampled rows (the first, the last, random)."""
-    print(f"[case] {mesh.name} cells={mesh.n_cells} prec={precision} sampled", flush=True)
+def _full_size_case(mesh, params, precision):
+    """Full-size run in the benchmark's launch configuration (whole path), every
+    row compared with the oracle; the worst block's row is printed."""
+    print(f"[case] {mesh.name} cells={mesh.n_cells} prec={precision} full size", flush=True)
     pat = oracle.pattern(mesh)
     g = gpu_assemble(mesh, params, precision, full_path=True)
     check_pattern(g, pat)
-    rng = np.random.default_rng(11)
-    rows = np.unique(np.concatenate([[0, mesh.n_cells - 1], rng.integers(0, mesh.n_cells, n_sample)]))
-    vals, rhs = oracle.assemble(mesh, oracle_problem(params), rows=rows, pat=pat)
-    eb, er = block_errors(g, vals, rhs, pat, rows=rows)
-    print(f"       worst block {eb:.3e}  worst rhs row {er:.3e} over {len(rows)} rows", flush=True)
+    vals, rhs = oracle.assemble(mesh, oracle_problem(params), pat=pat)
+    where = {}
+    eb, er = block_errors(g, vals, rhs, pat, where=where)
+    r = where["row"]
+    print(f"       worst block {eb:.3e} (row {r}, p={mesh.cell_p[r]}, "
+          f"{mesh.cell_ptr[r + 1] - mesh.cell_ptr[r]} vertices, block {where['block']})  "
+          f"worst rhs row {er:.3e} over {mesh.n_cells} rows", flush=True)
     assert eb <= TOL[precision], eb
     assert er <= TOL[precision], er
 
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_workload3_mixed_degrees_full_size(precision):
-    _sampled_case(config_mesh(3), problem_params(3), precision)
+    _full_size_case(config_mesh(3), problem_params(3), precision)
 
 
-def test_workload5_p3_full_size():
-    _sampled_case(config_mesh(5), problem_params(5), 1)
+@pytest.mark.parametrize("precision", [1, 0])
+def test_workload5_p3_full_size(precision):
+    _full_size_case(config_mesh(5), problem_params(5), precision)
 
 
 @pytest.mark.parametrize("n_cells", [32768, 32800])
 def test_tile_sums_at_the_inline_limit(n_cells):
     # 1,024 tiles of 32 cells: the assembly adds up the tile sums before its
     # tile itself (up to 16 loads per lane); 1,025 tiles: the scan kernel runs
-    _sampled_case(voronoi_mesh(n_cells, 85, lloyd=0, p=2), DAR, 1, n_sample=200)
+    _full_size_case(voronoi_mesh(n_cells, 85, lloyd=0, p=2), DAR, 1)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_polynomial_data_and_full_path(precision):
     m = voronoi_mesh(333, 78, lloyd=2, p=2)
     _case(m, POLY, precision, full_path=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pure_advection(precision):
+    """a = 0 (the hyperbolic case): no diffusion terms and sigma = 0, so only the
+    element advection-reaction terms and the upwind face terms remain; on the
+    boundary only the inflow part (b . n < 0) carries the Dirichlet data."""
+    m = voronoi_mesh(700, 88, lloyd=1, p=1)
+    m = m.with_degrees(np.random.default_rng(10).integers(1, 5, m.n_cells))
+    _case(m, dict(a0=0.0, a1=0.0, b=(1.0, -0.4, 0.0), c=0.5, c_sigma=10.0, u="sin"), precision)
+    _case(m, dict(POLY, a0=0.0), precision)
 
 
 def test_cartesian_and_neumann():

@@ -78,6 +78,13 @@ def test_basis_traces_and_hierarchy():
         assert np.array_equal(phiq, phi4[:len(phiq)]) and np.array_equal(gq, g4[:len(phiq)])
 
 
+def _volume_points(m, c):
+    """Fan sub-triangles from the first vertex times the degree-4 rule (p <= 2)."""
+    xy = _cell_xy(m, c)
+    bary, _ = oracle.rules.triangle_rule(4)
+    return np.concatenate([bary @ np.stack([xy[0], xy[k], xy[k + 1]]) for k in range(1, len(xy) - 1)])
+
+
 def _cell_xy(m, c):
     ids = m.cell_vtx[m.cell_ptr[c]:m.cell_ptr[c + 1]]
     return np.stack([m.x[ids], m.y[ids]], 1)
@@ -124,4 +131,7 @@ def test_geometry_against_closed_forms():
         d = np.sqrt(((xy[:, None, :] - xy[None, :, :]) ** 2).sum(-1)).max()
         assert geo["diam"][c] == d
         assert np.array_equal(geo["lo"][c, :2], xy.min(0)) and np.array_equal(geo["hi"][c, :2], xy.max(0))
-        assert 1.5 <= geo["abar"][c] <= 2.5
+        # abar: a = 2 + 0.5 sin(2 pi x) cos(2 pi y) at the cell's volume points, maximised
+        pts = _volume_points(m, c)
+        ref = 2.0 + 0.5 * (np.sin(2 * np.pi * pts[:, 0]) * np.cos(2 * np.pi * pts[:, 1])).max()
+        assert abs(geo["abar"][c] - ref) <= 1e-14
