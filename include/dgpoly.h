@@ -10,9 +10,9 @@
  *   find u_h in S^p with B(u_h, v_h) = l(v_h) for all v_h       (Section 2.2)
  *   B = the symmetric interior penalty bilinear form   (equation dg-bilinear)
  *   l = the linear functional                          (equation dg-linear)
- *   sigma_F = C_sigma * max_{kappa in F} abar_kappa p_kappa^2 / h_kappa
- *             (Appendix A; h = diameter, abar = max of a over the element's
- *             volume quadrature points)
+ *   sigma_F = C_sigma * max_{kappa in F} abar_kappa p_kappa^2 / h_kappa, or the
+ *             covering form of Appendix A (dgp_problem.penalty; h = diameter,
+ *             abar = max of a over the element's volume quadrature points)
  * with physical-frame orthonormal Legendre bases of total degree p on each
  * element's bounding box (Section 3.1), quadrature on the fan sub-triangles of
  * each polygon and Gauss-Legendre points on each edge (Section 3), written into
@@ -100,6 +100,19 @@ typedef struct {
     const int32_t *face_opp;      /* [n_faces] 3D only (may be NULL in 2D) */
 } dgp_mesh_desc;
 
+/* Penalty sigma_F on a face F shared by elements kappa_1, kappa_2 (Appendix A;
+ * on a boundary face kappa_1 only), abar_kappa = max of a over the element's
+ * volume quadrature points:
+ *   DGP_PEN_DIAMETER  C_sigma max_kappa abar p^2 / h_kappa (h = diameter)
+ *   DGP_PEN_COVERING  C_sigma max_kappa abar p^2 |F| min(1 / |K^F|, C_cov / |kappa|)
+ *                     with the element's fan sub-triangles as its covering, K^F
+ *                     the sub-triangle having F as a side (v0 v1 v2 for the
+ *                     first edge, v0 v_{n-2} v_{n-1} for the last, v0 v_k v_k+1
+ *                     for edge k otherwise) and C_cov = p^2, every element taken
+ *                     as p-coverable; 2D meshes only (DGP_EUNSUPPORTED in 3D) */
+#define DGP_PEN_DIAMETER 0
+#define DGP_PEN_COVERING 1
+
 /* -div(a grad u) + b . grad u + c u = f, a(x) = a0 + a1 sin(2 pi x) cos(2 pi y)
  * (3D meshes: a1 must be 0, DGP_EUNSUPPORTED otherwise), b and c constant;
  * f, Dirichlet data g_D = u and Neumann data g_N = n . (a grad u) come from the
@@ -111,6 +124,7 @@ typedef struct {
     double c_sigma;    /* penalty constant C_sigma (10 in every workload) */
     int32_t u_kind;    /* DGP_U_SIN or DGP_U_POLY */
     double u_poly[10];
+    int32_t penalty;   /* DGP_PEN_DIAMETER or DGP_PEN_COVERING */
 } dgp_problem;
 
 typedef struct {

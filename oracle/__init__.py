@@ -28,6 +28,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 U_SIN, U_POLY = 0, 1
 T_VOLUME, T_INTERIOR, T_BOUNDARY, T_RHS, T_ALL = 1, 2, 4, 8, 15
+PEN_DIAMETER, PEN_COVERING = 0, 1
 
 
 def build(force: bool = False) -> str:
@@ -53,7 +54,7 @@ class _Mesh(C.Structure):
 class _Problem(C.Structure):
     _fields_ = [("a0", C.c_double), ("a1", C.c_double), ("b", C.c_double * 3), ("c", C.c_double),
                 ("c_sigma", C.c_double), ("u_kind", C.c_int32), ("u_poly", C.c_double * 10),
-                ("term_mask", C.c_int32), ("sigma_override", C.c_double)]
+                ("term_mask", C.c_int32), ("sigma_override", C.c_double), ("penalty", C.c_int32)]
 
 
 class _Rule(C.Structure):
@@ -76,6 +77,7 @@ class Problem:
     u_poly: tuple = field(default_factory=lambda: (0.0,) * 10)
     term_mask: int = T_ALL
     sigma_override: float = -1.0
+    penalty: int = PEN_DIAMETER
 
     def _struct(self) -> _Problem:
         s = _Problem()
@@ -88,13 +90,15 @@ class Problem:
             s.u_poly[i] = up[i]
         s.term_mask = self.term_mask
         s.sigma_override = self.sigma_override
+        s.penalty = self.penalty
         return s
 
     @staticmethod
     def from_params(d: dict) -> "Problem":
         return Problem(a0=d["a0"], a1=d["a1"], b=tuple(d["b"]), c=d["c"], c_sigma=d.get("c_sigma", 10.0),
                        u_kind=U_SIN if d.get("u", "sin") == "sin" else U_POLY,
-                       u_poly=tuple(d.get("u_poly", (0.0,) * 10)))
+                       u_poly=tuple(d.get("u_poly", (0.0,) * 10)),
+                       penalty=PEN_COVERING if d.get("penalty", "diameter") == "covering" else PEN_DIAMETER)
 
 
 _lib = None

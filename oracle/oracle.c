@@ -454,6 +454,49 @@ static int face_points(const orc_mesh *m, const orc_rules *ru, int32_t f, int64_
     return 0;
 }
 
+/* ---------------------------------------------------------------- penalty */
+/* Appendix A, one side of face f in 2D: the covering is the fan of cell c
+ * (triangles (v0, v_t, v_t+1), t = 1..n-2); the sub-triangle having the edge
+ * (v_k, v_k+1) as a side is t = k, except t = 1 for k = 0 and t = n - 2 for
+ * k = n - 1.  Returns abar p^2 |F| min(1 / |K^F|, C_cov / |kappa|), C_cov = p^2,
+ * or -1 if f is not an edge of c. */
+static double covering_side(const orc_mesh *m, const cellgeo *g, int64_t c, int32_t f, double flen) {
+    int64_t s = m->cell_ptr[c], n = m->cell_ptr[c + 1] - s;
+    int64_t k = -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (m->cell_face[s + i] == f) k = i;
+    if (k < 0) return -1.0;
+    int64_t t = k == 0 ? 1 : (k == n - 1 ? n - 2 : k);
+    double v0[3], v1[3], v2[3];
+    vtx(m, m->cell_vtx[s], v0);
+    vtx(m, m->cell_vtx[s + t], v1);
+    vtx(m, m->cell_vtx[s + t + 1], v2);
+    double kf = 0.5 * fabs((v1[0] - v0[0]) * (v2[1] - v0[1]) - (v2[0] - v0[0]) * (v1[1] - v0[1]));
+    int p = m->cell_p[c];
+    double inv_k = 1.0 / kf; /* a degenerate sub-triangle leaves the C_cov bound */
+    double cov = (double)(p * p) / g->meas;
+    return g->abar * p * p * flen * (inv_k < cov ? inv_k : cov);
+}
+
+/* sigma_F (Appendix A) for face f of row r; o = the other element or -1 */
+static double face_sigma(const orc_mesh *m, const orc_problem *pr, const cellgeo *geo, int64_t r, int32_t o,
+                         int32_t f, double flen) {
+    if (pr->sigma_override >= 0) return pr->sigma_override;
+    int p_r = m->cell_p[r];
+    if (pr->penalty == ORC_PEN_COVERING) {
+        double s1 = covering_side(m, &geo[r], r, f, flen);
+        double s2 = o >= 0 ? covering_side(m, &geo[o], o, f, flen) : 0.0;
+        return pr->c_sigma * (s1 > s2 ? s1 : s2);
+    }
+    double s1 = geo[r].abar * p_r * p_r / geo[r].diam;
+    double s2 = 0.0;
+    if (o >= 0) {
+        int p_o = m->cell_p[o];
+        s2 = geo[o].abar * p_o * p_o / geo[o].diam;
+    }
+    return pr->c_sigma * (s1 > s2 ? s1 : s2);
+}
+
 static double dotn(const double *g, const double *n, int dim) {
     double s = 0.0;
     for (int d = 0; d < dim; ++d) s += g[d] * n[d];
@@ -528,8 +571,7 @@ static int assemble_row(const orc_mesh *m, const orc_problem *pr, const orc_rule
             if (!(pr->term_mask & ORC_T_INTERIOR)) continue;
             const cellgeo *go = &geo[o];
             int nbo = orc_nb(dim, po);
-            double s1 = gr->abar * pr_ * pr_ / gr->diam, s2 = go->abar * po * po / go->diam;
-            double sigma = pr->sigma_override >= 0 ? pr->sigma_override : pr->c_sigma * (s1 > s2 ? s1 : s2);
+            double sigma = face_sigma(m, pr, geo, r, o, f, fp.meas);
             int64_t kc = -1;
             for (int64_t kk = k0; kk < k1; ++kk)
                 if (col_idx[kk] == o) kc = kk;
@@ -559,7 +601,7 @@ static int assemble_row(const orc_mesh *m, const orc_problem *pr, const orc_rule
                 }
             }
         } else if (m->face_bc[f] == 1) {
-            double sigma = pr->sigma_override >= 0 ? pr->sigma_override : pr->c_sigma * gr->abar * pr_ * pr_ / gr->diam;
+            double sigma = face_sigma(m, pr, geo, r, -1, f, fp.meas);
             for (int q = 0; q < fp.npts; ++q) {
                 const double *x = fp.X + 3 * q;
                 double w = fp.W[q];
@@ -606,6 +648,8 @@ int orc_assemble(const orc_mesh *m, const orc_problem *pr, const orc_rules *ru,
                  const int64_t *dof_ptr, const int64_t *rows, int64_t n_rows,
                  double *vals, double *rhs) {
     if (!m || !pr || !ru || (m->dim != 2 && m->dim != 3)) return -1;
+    if (pr->penalty != ORC_PEN_DIAMETER && pr->penalty != ORC_PEN_COVERING) return -1;
+    if (pr->penalty == ORC_PEN_COVERING && m->dim != 2) return -3;
     leg_init();
     for (int64_t c = 0; c < m->n_cells; ++c)
         if (m->cell_p[c] < 0 || m->cell_p[c] > MAXP || (m->dim == 2 && m->cell_p[c] > 4)) return -3;

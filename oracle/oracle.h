@@ -9,7 +9,9 @@
  *   bilinear form B(w, v)   -- Section 2.2, equation (dg-bilinear)
  *   linear functional l(v)  -- Section 2.2, equation (dg-linear)
  *   penalty sigma           -- Appendix A, read as sigma_F =
- *                              C_sigma * max_{kappa in F} abar_kappa p_kappa^2 / h_kappa
+ *                              C_sigma * max_{kappa in F} abar_kappa p_kappa^2 / h_kappa,
+ *                              or (2D) with the covering factor of Appendix A
+ *                              (fan sub-triangles as the covering)
  *   basis                   -- Section 3.1: orthonormal tensor Legendre
  *                              polynomials of total degree p on the element's
  *                              bounding box, physical frame, hierarchical order
@@ -61,7 +63,16 @@ typedef struct {
     double u_poly[10];      /* 1, x, y, z, x^2, y^2, z^2, xy, xz, yz */
     int32_t term_mask;      /* ORC_T_* bits: which terms to assemble */
     double sigma_override;  /* < 0: penalty formula; >= 0: this constant */
+    int32_t penalty;        /* ORC_PEN_DIAMETER or ORC_PEN_COVERING */
 } orc_problem;
+
+/* Penalty formulas (Appendix A):
+ *   ORC_PEN_DIAMETER  sigma_F = C_sigma max_kappa abar p^2 / h_kappa
+ *   ORC_PEN_COVERING  sigma_F = C_sigma max_kappa abar p^2 |F| min(1 / |K^F|, C_cov / |kappa|)
+ *                     with the fan sub-triangles as the covering, K^F the one
+ *                     having F as a side, C_cov = p^2 (2D; every element taken
+ *                     as p-coverable) */
+enum { ORC_PEN_DIAMETER = 0, ORC_PEN_COVERING = 1 };
 
 typedef struct {
     int32_t n;

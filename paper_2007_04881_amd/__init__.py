@@ -18,6 +18,7 @@ F64, F32 = 0, 1
 U_SIN, U_POLY = 0, 1
 RULE_PLAIN, RULE_REDUCED = 0, 1
 INIT_NETWORK, INIT_TEMPLATE = 0, 1
+PEN_DIAMETER, PEN_COVERING = 0, 1
 MLP_PARAMS = 43952
 
 _STATUS = {0: "DGP_OK", -1: "DGP_EINVAL", -2: "DGP_EMESH", -3: "DGP_EUNSUPPORTED", -4: "DGP_ENOMEM",
@@ -41,7 +42,8 @@ class MeshDesc(C.Structure):
 
 class ProblemDesc(C.Structure):
     _fields_ = [("a0", C.c_double), ("a1", C.c_double), ("b", C.c_double * 3), ("c", C.c_double),
-                ("c_sigma", C.c_double), ("u_kind", C.c_int32), ("u_poly", C.c_double * 10)]
+                ("c_sigma", C.c_double), ("u_kind", C.c_int32), ("u_poly", C.c_double * 10),
+                ("penalty", C.c_int32)]
 
 
 class PatternInfo(C.Structure):
@@ -121,7 +123,7 @@ def lib():
 
 
 def problem_desc(params: dict) -> ProblemDesc:
-    """ProblemDesc from a plain dict (a0, a1, b, c, c_sigma, u, u_poly)."""
+    """ProblemDesc from a plain dict (a0, a1, b, c, c_sigma, u, u_poly, penalty)."""
     p = ProblemDesc()
     p.a0, p.a1, p.c = params["a0"], params["a1"], params["c"]
     p.c_sigma = params.get("c_sigma", 10.0)
@@ -132,6 +134,7 @@ def problem_desc(params: dict) -> ProblemDesc:
     up = list(params.get("u_poly", ())) + [0.0] * 10
     for i in range(10):
         p.u_poly[i] = up[i]
+    p.penalty = PEN_COVERING if params.get("penalty", "diameter") == "covering" else PEN_DIAMETER
     return p
 
 

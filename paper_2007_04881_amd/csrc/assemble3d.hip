@@ -688,8 +688,15 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
                 }
             }
             if (code < 0) {
+                // boundary data with sin/cos taken directly, not by angle addition
+                // from the centre: on a boundary where the manufactured u vanishes
+                // (sin(pi k) = 0) the direct evaluation is exactly zero, where angle
+                // addition leaves a rounding residue that the large penalty carries
+                // into the load of elements whose load is itself tiny (corners)
+                Trig3 tb = tc;
+                tb.near = false;
                 double ue, gu[3];
-                exact3(pr, tc, fp.x, &ue, gu, nullptr);
+                exact3(pr, tb, fp.x, &ue, gu, nullptr);
                 if (code == -1) {
                     const T r0 = T(ha * ue), r1 = T(hs * ue);
 #pragma unroll

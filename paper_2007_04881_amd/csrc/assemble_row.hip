@@ -168,6 +168,7 @@ struct RowCtx {
     bool red;
     uint64_t gmask;
     double ex, ey, x0, y0, isq, hx, hy, pen_r;  // x0, y0: the fan apex (first vertex)
+    int64_t s0;                                 // the row's first loop entry (cell_ptr)
     int64_t pre_v, pre_d;
     Box bx;
     TrigCentre tc;
@@ -401,7 +402,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             // the lane's point and weight: a fan sub-triangle point, or point gq
             // of its edge (canonical order: lower vertex id first)
             const bool vpt = vol && !R.red;
-            double px = 0.0, py = 0.0, W = 0.0, nx = 0.0, ny = 0.0, up = 0.0;
+            double px = 0.0, py = 0.0, W = 0.0, nx = 0.0, ny = 0.0, up = 0.0, flen = 0.0;
             if (vpt) {
                 const int qi = q - tri * C::NQT;
                 const double area = 0.5 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
@@ -414,6 +415,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                 const double xa = fwd ? X1 : X2, ya = fwd ? Y1 : Y2;
                 const double tx = (fwd ? X2 : X1) - xa, ty = (fwd ? Y2 : Y1) - ya;
                 const double len = sqrt(tx * tx + ty * ty);
+                flen = len;
                 const double dl = (fwd ? 1.0 : -1.0) / len;
                 nx = ty * dl;  // outward for a CCW loop
                 ny = -tx * dl;
@@ -459,7 +461,11 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                 xi = (px - bx.mx) * bx.cx;
                 eta = (py - bx.my) * bx.cy;
                 if (og >= 0) {
-                    const double sigma = pr.c_sigma * (R.pen_r > pen_o ? R.pen_r : pen_o);
+                    double sigma = pr.c_sigma * (R.pen_r > pen_o ? R.pen_r : pen_o);
+                    if (pr.penalty == 1) {
+                        const int F = m.cell_face[R.s0 + fk];
+                        sigma = pr.c_sigma * flen * fmax(A.pen_face[2 * F], A.pen_face[2 * F + 1]);
+                    }
                     const double ha = -0.5 * w * pdn.a, hs = (sigma - up) * w;
                     pc.b0 = T(ha * cnx);
                     pc.b1 = T(ha * cny);
@@ -471,7 +477,8 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                     xin = (px - bo.mx) * bo.cx;
                     etan = (py - bo.my) * bo.cy;
                 } else if (og == -1) {
-                    const double sigma = pr.c_sigma * R.pen_r;
+                    double sigma = pr.c_sigma * R.pen_r;
+                    if (pr.penalty == 1) sigma = pr.c_sigma * flen * A.pen_face[2 * m.cell_face[R.s0 + fk]];
                     const PointData pd = point_data(pr, px, py, false);
                     const double ha = -w * pd.a, hs = (sigma - up) * w;
                     pc.b0 = T(ha * cnx);
@@ -708,6 +715,7 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     R.tc.cy = uniform(R.tc.cy);
     R.tc.near = __builtin_amdgcn_readfirstlane(R.tc.near);
     R.pen_r = uniform(g.abar * P * P / g.h);
+    R.s0 = s;
     R.red = A.reduced && A.qr_ok[c];
     R.QM = R.red ? kQrNodes : (nv - 2) * C::NQT;  // points of the element matrix
     R.QF0 = (R.QM + FG - 1) / FG * FG;            // edge groups start here

@@ -75,6 +75,9 @@ struct PrepOut {
     int32_t *cnt;        // [n_cells][4] blocks, values, dofs before the element in its tile; diagonal rank | offset << 8
     int32_t *tile_sum;   // [n_tiles][4]: blocks, values and dofs of the tile, then 0
     int64_t *tile_off;   // [n_tiles + 1][3] exclusive prefix of the tile sums (totals last)
+    // covering penalty only: [2 n_faces] abar p^2 min(1 / |K^F|, p^2 / |kappa|) of the
+    // face's left (2 f) and right (2 f + 1) element; sigma_F = C_sigma |F| max of the two
+    double *pen_face;
 };
 
 // Problem data as the kernels see it.
@@ -83,6 +86,7 @@ struct DevProblem {
     double bz;  // 3D only
     int32_t u_kind;  // 0 sines, 1 polynomial
     double u[10];
+    int32_t penalty;  // 0: C abar p^2 / h; 1: the covering form (pen_face)
 };
 
 __host__ __device__ constexpr int nb2d(int p) { return (p + 1) * (p + 2) / 2; }
@@ -263,6 +267,7 @@ struct AsmArgs {
     const int4 *tile_sum = nullptr;
     int32_t n_tiles = 0;
     const EdgeRec *erec;
+    const double *pen_face;  // covering penalty (PrepOut::pen_face)
     int64_t *row_ptr;
     int32_t *col_idx;
     int64_t *val_ptr;

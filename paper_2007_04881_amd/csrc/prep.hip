@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     }
 
     // neighbours across this lane's edges and the edges' start vertices
-    int nb[SLOTS], nbsz[SLOTS], code[SLOTS], vq[SLOTS];
+    int nb[SLOTS], nbsz[SLOTS], code[SLOTS], vq[SLOTS], fq[SLOTS];
     double xq[SLOTS], yq[SLOTS];
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
@@ -116,9 +116,11 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
         nbsz[q] = 0;
         code[q] = 0;
         vq[q] = 0;
+        fq[q] = -1;
         xq[q] = yq[q] = 0.0;
         if (f < nv) {
             const int F = m.cell_face[s + f];
+            fq[q] = F;
             const int o = other_cell(m, F, c);
             code[q] = o >= 0 ? o : -(int)m.face_bc[F];
             out.nbr[s + f] = code[q];
@@ -274,6 +276,26 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
         }
     }
 
+    if (valid && pr.penalty == 1) {
+        // covering penalty (Appendix A): this element's side of each of its faces,
+        // the fan sub-triangle having the face as a side
+        const double area = 0.5 * a2;
+        const double abar = pr.a1 != 0.0 ? amax : pr.a0;
+        const double cov = double(p * p) / area;
+        const double2 v0 = s_xy[grp][0];
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+            const int f = lane + G * q;
+            if (f < nv) {
+                const int t = f == 0 ? 1 : (f == nv - 1 ? nv - 2 : f);
+                const double2 v1 = s_xy[grp][t], v2 = s_xy[grp][t + 1];
+                const double kf = 0.5 * fabs((v1.x - v0.x) * (v2.y - v0.y) - (v2.x - v0.x) * (v1.y - v0.y));
+                const double inv = 1.0 / kf;  // a degenerate sub-triangle leaves the C_cov bound
+                const int side = m.face_cell[2 * fq[q]] == c ? 0 : 1;
+                out.pen_face[2 * fq[q] + side] = abar * double(p * p) * (inv < cov ? inv : cov);
+            }
+        }
+    }
     if (valid && lane == 0) {
         CellGeo g;
         g.lox = lox;

@@ -70,6 +70,56 @@ static dgp_status upload(dgp_ctx *c, const T *src, int64_t n, const T **dst) {
     return DGP_OK;
 }
 
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// The preparation outputs of one step (2D: per-face penalty sides, cell
+// records, edge neighbours and records, row counts, tile sums and offsets)
+// carved from one buffer at base;
+// with base = null only the size is computed.  Returns the size in bytes.
+static size_t layout2d(int64_t N, int64_t nnz_v, int64_t F, int n_tiles, char *base, PrepOut *o) {
+    const size_t o_pen = 0;
+    const size_t o_geo = o_pen + align256(sizeof(double) * 2 * (size_t)F);
+    const size_t o_nbr = o_geo + align256(sizeof(CellGeo) * (size_t)N);
+    const size_t o_erec = o_nbr + align256(sizeof(int32_t) * (size_t)nnz_v);
+    const size_t o_cnt = o_erec + align256(sizeof(EdgeRec) * (size_t)nnz_v);
+    const size_t o_tile = o_cnt + align256(sizeof(int32_t) * 4 * (size_t)N);
+    const size_t o_off = o_tile + align256(sizeof(int32_t) * 4 * (size_t)n_tiles);
+    const size_t bytes = o_off + sizeof(int64_t) * 3 * (size_t)(n_tiles + 1);
+    if (base && o) {
+        o->pen_face = reinterpret_cast<double *>(base + o_pen);
+        o->geo = reinterpret_cast<CellGeo *>(base + o_geo);
+        o->nbr = reinterpret_cast<int32_t *>(base + o_nbr);
+        o->erec = reinterpret_cast<EdgeRec *>(base + o_erec);
+        o->cnt = reinterpret_cast<int32_t *>(base + o_cnt);
+        o->tile_sum = reinterpret_cast<int32_t *>(base + o_tile);
+        o->tile_off = reinterpret_cast<int64_t *>(base + o_off);
+    }
+    return bytes;
+}
+
+// The same for polyhedra: cell records, face order and groups, row counts,
+// tile sums and offsets, and the limit flag (which must start at zero).
+static size_t layout3d(int64_t N, int64_t n_cf, int n_tiles, char *base, Prep3Out *o) {
+    const size_t o_geo = 0;
+    const size_t o_ord = o_geo + align256(sizeof(CellGeo3) * (size_t)N);
+    const size_t o_grp = o_ord + align256(sizeof(int32_t) * (size_t)n_cf);
+    const size_t o_cnt = o_grp + align256(sizeof(FaceGroup) * (size_t)n_cf);
+    const size_t o_tile = o_cnt + align256(sizeof(int32_t) * 4 * (size_t)N);
+    const size_t o_off = o_tile + align256(sizeof(int64_t) * 3 * (size_t)n_tiles);
+    const size_t o_err = o_off + align256(sizeof(int64_t) * 3 * (size_t)(n_tiles + 1));
+    const size_t bytes = o_err + 256;
+    if (base && o) {
+        o->geo = reinterpret_cast<CellGeo3 *>(base + o_geo);
+        o->forder = reinterpret_cast<int32_t *>(base + o_ord);
+        o->grp = reinterpret_cast<FaceGroup *>(base + o_grp);
+        o->cnt = reinterpret_cast<int32_t *>(base + o_cnt);
+        o->tile_sum = reinterpret_cast<int64_t *>(base + o_tile);
+        o->tile_off = reinterpret_cast<int64_t *>(base + o_off);
+        o->err = reinterpret_cast<int32_t *>(base + o_err);
+    }
+    return bytes;
+}
+
 extern "C" {
 
 dgp_status dgp_create(dgp_ctx **out, int device, void *hip_stream) {
@@ -252,13 +302,7 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     // geometry records, edge neighbours, row sizes and their tile sums
     const int64_t nnzb_max = N + nnz_v;
     ctx->n_tiles = (int)((N + kPrepTile - 1) / kPrepTile);
-    const size_t o_geo = 0;
-    const size_t o_nbr = o_geo + sizeof(CellGeo) * (size_t)N;
-    const size_t o_erec = o_nbr + ((sizeof(int32_t) * (size_t)nnz_v + 255) & ~size_t(255));
-    const size_t o_cnt = o_erec + ((sizeof(EdgeRec) * (size_t)nnz_v + 255) & ~size_t(255));
-    const size_t o_tile = o_cnt + sizeof(int32_t) * 4 * (size_t)N;
-    const size_t o_off = o_tile + ((sizeof(int32_t) * 4 * (size_t)ctx->n_tiles + 255) & ~size_t(255));
-    const size_t work_bytes = o_off + sizeof(int64_t) * 3 * (size_t)(ctx->n_tiles + 1);
+    const size_t work_bytes = layout2d(N, nnz_v, F, ctx->n_tiles, nullptr, nullptr);
     if (hipMalloc(&ctx->row_ptr, sizeof(int64_t) * (N + 1)) != hipSuccess ||
         hipMalloc(&ctx->col_idx, sizeof(int32_t) * nnzb_max) != hipSuccess ||
         hipMalloc(&ctx->val_ptr, sizeof(int64_t) * (nnzb_max + 1)) != hipSuccess ||
@@ -268,13 +312,7 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
         return fail(ctx, DGP_ENOMEM, "device allocation failed");
     }
     HIPCHK(ctx, hipMemset(ctx->work, 0, work_bytes));
-    char *b = static_cast<char *>(ctx->work);
-    ctx->prep.geo = reinterpret_cast<CellGeo *>(b + o_geo);
-    ctx->prep.nbr = reinterpret_cast<int32_t *>(b + o_nbr);
-    ctx->prep.erec = reinterpret_cast<EdgeRec *>(b + o_erec);
-    ctx->prep.cnt = reinterpret_cast<int32_t *>(b + o_cnt);
-    ctx->prep.tile_sum = reinterpret_cast<int32_t *>(b + o_tile);
-    ctx->prep.tile_off = reinterpret_cast<int64_t *>(b + o_off);
+    layout2d(N, nnz_v, F, ctx->n_tiles, static_cast<char *>(ctx->work), &ctx->prep);
     if (pmin != pmax) {
         // mixed degrees: one launch per degree over the elements of that degree (in id order)
         std::vector<int32_t> rows((size_t)N);
@@ -437,15 +475,7 @@ static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
 #undef UP
     const int64_t nnzb_max = N + n_cf;
     ctx->n_tiles = (int)((N + kPrepTile3D - 1) / kPrepTile3D);
-    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    const size_t o_geo = 0;
-    const size_t o_ord = o_geo + al(sizeof(CellGeo3) * (size_t)N);
-    const size_t o_grp = o_ord + al(sizeof(int32_t) * (size_t)n_cf);
-    const size_t o_cnt = o_grp + al(sizeof(FaceGroup) * (size_t)n_cf);
-    const size_t o_tile = o_cnt + al(sizeof(int32_t) * 4 * (size_t)N);
-    const size_t o_off = o_tile + al(sizeof(int64_t) * 3 * (size_t)ctx->n_tiles);
-    const size_t o_err = o_off + al(sizeof(int64_t) * 3 * (size_t)(ctx->n_tiles + 1));
-    const size_t work_bytes = o_err + 256;
+    const size_t work_bytes = layout3d(N, n_cf, ctx->n_tiles, nullptr, nullptr);
     if (hipMalloc(&ctx->row_ptr, sizeof(int64_t) * (N + 1)) != hipSuccess ||
         hipMalloc(&ctx->col_idx, sizeof(int32_t) * nnzb_max) != hipSuccess ||
         hipMalloc(&ctx->val_ptr, sizeof(int64_t) * (nnzb_max + 1)) != hipSuccess ||
@@ -455,14 +485,7 @@ static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
         return fail(ctx, DGP_ENOMEM, "device allocation failed");
     }
     HIPCHK(ctx, hipMemset(ctx->work, 0, work_bytes));
-    char *b = static_cast<char *>(ctx->work);
-    ctx->prep3.geo = reinterpret_cast<CellGeo3 *>(b + o_geo);
-    ctx->prep3.forder = reinterpret_cast<int32_t *>(b + o_ord);
-    ctx->prep3.grp = reinterpret_cast<FaceGroup *>(b + o_grp);
-    ctx->prep3.cnt = reinterpret_cast<int32_t *>(b + o_cnt);
-    ctx->prep3.tile_sum = reinterpret_cast<int64_t *>(b + o_tile);
-    ctx->prep3.tile_off = reinterpret_cast<int64_t *>(b + o_off);
-    ctx->prep3.err = reinterpret_cast<int32_t *>(b + o_err);
+    layout3d(N, n_cf, ctx->n_tiles, static_cast<char *>(ctx->work), &ctx->prep3);
     if (pmin != pmax) {
         std::vector<int32_t> rows((size_t)N);
         int64_t cnt[kMaxP + 2] = {};
@@ -562,6 +585,7 @@ static DevProblem to_dev(const dgp_problem *p) {
     d.c_sigma = p->c_sigma;
     d.u_kind = p->u_kind;
     for (int i = 0; i < 10; ++i) d.u[i] = p->u_poly[i];
+    d.penalty = p->penalty;
     return d;
 }
 
@@ -572,6 +596,10 @@ static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int
     if (precision != DGP_F64 && precision != DGP_F32) return fail(ctx, DGP_EINVAL, "precision %d", precision);
     if (prob->u_kind != DGP_U_SIN && prob->u_kind != DGP_U_POLY) return fail(ctx, DGP_EINVAL, "u_kind");
     if (!(prob->c_sigma >= 0.0)) return fail(ctx, DGP_EINVAL, "c_sigma must be >= 0");
+    if (prob->penalty != DGP_PEN_DIAMETER && prob->penalty != DGP_PEN_COVERING)
+        return fail(ctx, DGP_EINVAL, "penalty %d", prob->penalty);
+    if (prob->penalty == DGP_PEN_COVERING && ctx->dim == 3)
+        return fail(ctx, DGP_EUNSUPPORTED, "the covering penalty is built for 2D meshes");
     if (rule_mode != DGP_RULE_PLAIN && rule_mode != DGP_RULE_REDUCED)
         return fail(ctx, DGP_EINVAL, "rule_mode %d", rule_mode);
     if (ctx->dim == 3) {
@@ -647,6 +675,7 @@ static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precis
     a.tile_sum = inline_tiles(ctx, values) ? reinterpret_cast<const int4 *>(ctx->prep.tile_sum) : nullptr;
     a.n_tiles = ctx->n_tiles;
     a.erec = ctx->prep.erec;
+    a.pen_face = ctx->prep.pen_face;
     a.rows = nullptr;
     a.n_rows = (int32_t)ctx->n_cells;
     a.row_ptr = ctx->row_ptr;
@@ -797,6 +826,7 @@ dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice) {
         a.tile_sum = inline_tiles(ctx, 1) ? reinterpret_cast<const int4 *>(ctx->prep.tile_sum) : nullptr;
         a.n_tiles = ctx->n_tiles;
         a.erec = ctx->prep.erec;
+        a.pen_face = ctx->prep.pen_face;
         a.row_ptr = ctx->row_ptr;
         a.col_idx = ctx->col_idx;
         a.val_ptr = ctx->val_ptr;

@@ -52,7 +52,11 @@ def block_errors(g, vals_ref, rhs_ref, pat, rows=None, where=None):
     b0, b1 = pat.val_ptr[blk], pat.val_ptr[blk + 1]
     worst_b = _segment_worst(g["vals"], vals_ref, b0, b1, what="block", where=where, ids=(brow, blk))
     d0, d1 = pat.dof_ptr[rows], pat.dof_ptr[rows + 1]
-    worst_r = _segment_worst(g["rhs"], rhs_ref, d0, d1, what="load", rows_for_abs=True)
+    rw = {}
+    worst_r = _segment_worst(g["rhs"], rhs_ref, d0, d1, what="load", rows_for_abs=True, where=rw,
+                             ids=(rows, rows))
+    if where is not None:
+        where.update(rhs_row=rw["row"])
     return worst_b, worst_r
 
 

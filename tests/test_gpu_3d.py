@@ -34,7 +34,7 @@ def _case(mesh, params, precision, rows=None):
     vals, rhs = oracle.assemble(mesh, oracle_problem(params), rows=rows, pat=pat)
     where = {}
     eb, er = block_errors(g, vals, rhs, pat, rows=rows, where=where)
-    print(f"       worst block {eb:.3e} (row {where['row']})  worst rhs row {er:.3e}", flush=True)
+    print(f"       worst block {eb:.3e} (row {where['row']})  worst rhs row {er:.3e} (row {where['rhs_row']})", flush=True)
     assert eb <= TOL[precision], eb
     assert er <= TOL[precision], er
     return g
@@ -167,6 +167,9 @@ def test_3d_error_paths():
     with pytest.raises(D.DgpError) as e:
         ctx.assemble(POISSON3, 1, vals, rhs, rule_mode=D.RULE_REDUCED)
     assert e.value.status in (-3, -6)
+    with pytest.raises(D.DgpError) as e:
+        ctx.assemble(dict(POISSON3, penalty="covering"), 1, vals, rhs)
+    assert e.value.status == -3
     ctx.close()
     # degree 3 is outside the 3D kernels
     ctx = D.Context(0)

@@ -30,7 +30,7 @@ def _case(mesh, params, precision, full_path=False):
     vals, rhs = oracle.assemble(mesh, oracle_problem(params), pat=pat)
     where = {}
     eb, er = block_errors(g, vals, rhs, pat, where=where)
-    print(f"       worst block {eb:.3e} (row {where['row']})  worst rhs row {er:.3e}", flush=True)
+    print(f"       worst block {eb:.3e} (row {where['row']})  worst rhs row {er:.3e} (row {where['rhs_row']})", flush=True)
     assert eb <= TOL[precision], eb
     assert er <= TOL[precision], er
     return g
@@ -76,7 +76,7 @@ def _full_size_case(mesh, params, precision):
     r = where["row"]
     print(f"       worst block {eb:.3e} (row {r}, p={mesh.cell_p[r]}, "
           f"{mesh.cell_ptr[r + 1] - mesh.cell_ptr[r]} vertices, block {where['block']})  "
-          f"worst rhs row {er:.3e} over {mesh.n_cells} rows", flush=True)
+          f"worst rhs row {er:.3e} (row {where['rhs_row']}) over {mesh.n_cells} rows", flush=True)
     assert eb <= TOL[precision], eb
     assert er <= TOL[precision], er
 
@@ -113,6 +113,22 @@ def test_pure_advection(precision):
     m = m.with_degrees(np.random.default_rng(10).integers(1, 5, m.n_cells))
     _case(m, dict(a0=0.0, a1=0.0, b=(1.0, -0.4, 0.0), c=0.5, c_sigma=10.0, u="sin"), precision)
     _case(m, dict(POLY, a0=0.0), precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_covering_penalty(precision):
+    """sigma_F of Appendix A with the fan sub-triangles as the covering (per face:
+    |F|, the sub-triangle having F as a side, |kappa|, C_cov = p^2), on mixed
+    degrees with variable a, and on octagons whose degenerate fan triangles
+    leave the C_cov bound and whose neighbours share two edges."""
+    m = voronoi_mesh(1000, 94, lloyd=1, p=1)
+    m = m.with_degrees(np.random.default_rng(13).integers(1, 5, m.n_cells))
+    _case(m, dict(DAR, penalty="covering"), precision)
+    _case(m, dict(POLY, penalty="covering"), precision, full_path=True)
+    s = split_cartesian_mesh(12, 10, p=2, x0=0.1, x1=1.3, y0=-0.2, y1=0.9)
+    _case(s, dict(DAR, penalty="covering"), precision)
+    g = voronoi_mesh(16384, 2007048812, lloyd=0, p=2)  # the benchmark's mesh size
+    _case(g, dict(DAR, penalty="covering"), precision, full_path=True)
 
 
 def test_cartesian_and_neumann():

@@ -117,3 +117,109 @@ def test_penalty_read_back_from_the_matrix(c_sigma):
                 assert np.abs(v[sl] - v0[sl] - ref * mass).max() <= 1e-9 * ref * np.abs(mass).max()
                 nb_checked += 1
     assert nb_checked > 2 * m.n_cells
+
+
+# ------------------------------------------------------------ covering penalty
+def _sigma_read_back(m, c_sigma, a0, a1, penalty, check):
+    """sigma_F per (row, block) read back from assembled interior / boundary terms;
+    check(r, c, sigma) is called for every cross block and every boundary diagonal block."""
+    pat = oracle.pattern(m)
+
+    def asm(mask, override):
+        pr = oracle.Problem(a0=a0, a1=a1, c_sigma=c_sigma, term_mask=mask, sigma_override=override,
+                            penalty=penalty)
+        return oracle.assemble(m, pr, pat=pat)[0]
+
+    faces = lambda r: set(m.cell_face[m.cell_face_ptr[r]:m.cell_face_ptr[r + 1]].tolist())
+    n = 0
+    for mask in (oracle.T_INTERIOR, oracle.T_BOUNDARY):
+        v, v0, v1 = asm(mask, -1.0), asm(mask, 0.0), asm(mask, 1.0)
+        for r in range(m.n_cells):
+            for k in range(pat.row_ptr[r], pat.row_ptr[r + 1]):
+                c = pat.col_idx[k]
+                if (mask == oracle.T_INTERIOR) == (c == r):
+                    continue
+                # blocks that one face alone contributes to (the penalty is per face)
+                if c == r:
+                    if sum(m.face_cell[2 * f + 1] < 0 for f in faces(r)) != 1:
+                        continue
+                elif len(faces(r) & faces(c)) != 1:
+                    continue
+                sl = slice(pat.val_ptr[k], pat.val_ptr[k + 1])
+                mass = v1[sl] - v0[sl]
+                if np.abs(mass).max() == 0.0:
+                    continue
+                j = np.argmax(np.abs(mass))
+                sigma = (v[sl][j] - v0[sl][j]) / mass[j]
+                # one sigma for the whole block (one face per block here)
+                assert np.abs(v[sl] - v0[sl] - sigma * mass).max() <= 1e-9 * abs(sigma) * np.abs(mass).max()
+                check(r, c, sigma)
+                n += 1
+    return n
+
+
+def test_covering_penalty_on_a_rectangular_grid():
+    """Cells hx x hy split into two fan triangles of area hx hy / 2, one of them
+    having each side as an edge: min(1 / |K^F|, p^2 / |kappa|) = min(2, p^2) / (hx hy),
+    so sigma_F = C_sigma a max_kappa p^2 min(2, p^2) |F| / (hx hy)."""
+    from meshgen import cartesian_mesh
+    nx, ny, x0, x1, y0, y1 = 3, 2, 0.1, 1.3, -0.2, 0.9
+    m = cartesian_mesh(nx, ny, p=1, x0=x0, x1=x1, y0=y0, y1=y1)
+    m = m.with_degrees(np.array([1, 2, 3, 3, 1, 2], np.int8))
+    hx, hy = (x1 - x0) / nx, (y1 - y0) / ny
+    a0 = 1.3
+    ix = lambda c: c % nx
+    factor = lambda p: p * p * min(2, p * p) / (hx * hy)
+
+    def check(r, c, sigma):
+        pr, pc = int(m.cell_p[r]), int(m.cell_p[c])
+        # a vertical face between columns, else a horizontal one (the middle
+        # column's single boundary face is horizontal too: c == r there)
+        flen = hy if ix(r) != ix(c) else hx
+        ref = 10.0 * a0 * max(factor(pr), factor(pc)) * flen
+        assert abs(sigma - ref) <= 1e-12 * ref, (r, c, sigma, ref)
+
+    n = _sigma_read_back(m, 10.0, a0, 0.0, oracle.PEN_COVERING, check)
+    # seven interior faces seen from both sides, and the middle column's two
+    # elements with one boundary face each (the corners have two)
+    assert n == 2 * 7 + 2
+
+
+def test_covering_penalty_on_voronoi_cells():
+    """Mixed degrees, variable a: sigma_F from the fan triangles computed here."""
+    m = _mesh()
+    abar = np.array([_a(*_volume_points(m, c).T).max() for c in range(m.n_cells)])
+    area = np.array([0.5 * np.sum(_xy(m, c)[:, 0] * np.roll(_xy(m, c)[:, 1], -1)
+                                  - np.roll(_xy(m, c)[:, 0], -1) * _xy(m, c)[:, 1]) for c in range(m.n_cells)])
+
+    def side(c, f):
+        s, e = m.cell_ptr[c], m.cell_ptr[c + 1]
+        n = e - s
+        k = int(np.where(m.cell_face[s:e] == f)[0][0])
+        t = 1 if k == 0 else (n - 2 if k == n - 1 else k)
+        xy = _xy(m, c)
+        v0, v1, v2 = xy[0], xy[t], xy[t + 1]
+        kf = 0.5 * abs((v1[0] - v0[0]) * (v2[1] - v0[1]) - (v2[0] - v0[0]) * (v1[1] - v0[1]))
+        a, b = m.face_vtx[2 * f], m.face_vtx[2 * f + 1]
+        flen = np.hypot(m.x[a] - m.x[b], m.y[a] - m.y[b])
+        p = int(m.cell_p[c])
+        return abar[c] * p * p * flen * min(1.0 / kf, p * p / area[c])
+
+    # faces between r and c (Voronoi neighbours share one edge)
+    def shared(r, c):
+        fr = set(m.cell_face[m.cell_face_ptr[r]:m.cell_face_ptr[r + 1]].tolist())
+        fc = set(m.cell_face[m.cell_face_ptr[c]:m.cell_face_ptr[c + 1]].tolist())
+        return sorted(fr & fc)
+
+    def check(r, c, sigma):
+        if c == r:
+            bf = [f for f in m.cell_face[m.cell_face_ptr[r]:m.cell_face_ptr[r + 1]] if m.face_cell[2 * f + 1] < 0]
+            ref = 3.5 * side(r, bf[0])
+        else:
+            fs = shared(r, c)
+            assert len(fs) == 1
+            ref = 3.5 * max(side(r, fs[0]), side(c, fs[0]))
+        assert abs(sigma - ref) <= 1e-12 * ref, (r, c, sigma, ref)
+
+    n = _sigma_read_back(m, 3.5, A0, A1, oracle.PEN_COVERING, check)
+    assert n > 2 * m.n_cells
