@@ -78,35 +78,112 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(mesh, info, val_bytes):
-    """Bytes the assembly kernel must move at least once: mesh connectivity and
-    coordinates, per-cell geometry records, the pattern it reads, and the values
-    and right-hand side it writes."""
+def algorithmic_bytes(mesh, info, val_bytes, with_pattern=False):
+    """Bytes the 2D assembly kernel must move at least once in the launch that is
+    timed (values only: the timing re-launch leaves the pattern arrays alone):
+    mesh connectivity and coordinates, the per-cell geometry records, and the
+    values and right-hand side it writes; with_pattern adds the pattern arrays
+    a pattern-writing launch stores."""
     V, N, F = mesh.n_vertices, mesh.n_cells, mesh.n_faces
     nv = int(mesh.cell_ptr[-1])
     reads = 16 * V + 8 * (N + 1) + 4 * nv + 4 * nv + 8 * F + F + 64 * N
-    reads += 8 * (N + 1) + 4 * info.nnzb + 8 * (info.nnzb + 1) + 8 * (N + 1)
     writes = val_bytes * (info.n_vals + info.n_dofs)
+    if with_pattern:
+        writes += 8 * (N + 1) + 4 * info.nnzb + 8 * (info.nnzb + 1) + 8 * (N + 1)
     return reads + writes
 
 
-def cpu_baseline(mesh, params, budget_s=12.0):
-    """The oracle as it stands (single-threaded FP64 C) on the same mesh:
-    pattern + full assembly, repeated until about budget_s seconds of work."""
+def algorithmic_bytes_3d(mesh, info, val_bytes):
+    """The same for polyhedra: tetrahedron ids, vertex coordinates, face arrays
+    (vertices, cells, code, opposite vertex), cell-face lists, values and load."""
+    V, N, F = mesh.n_vertices, mesh.n_cells, mesh.n_faces
+    nt = int(mesh.cell_ptr[-1]) // 4
+    ncf = int(mesh.cell_face_ptr[-1])
+    reads = 24 * V + 16 * nt + 8 * (N + 1) * 2 + (12 + 8 + 1 + 4) * F + 4 * ncf + 144 * N
+    return reads + val_bytes * (info.n_vals + info.n_dofs)
+
+
+def flops_3d(mesh, info, nb=10, q_tet=11, q_tri=6):
+    """Algorithmic FLOPs of one 3D assembly: the contraction Phi^T diag(w) Phi of
+    every element and face block counted once, 2 K n_b n_b' per block, K = 3 Q
+    (diffusion, d = 3) for the element block, K = 2 q per face block (two
+    self and two cross blocks per interior face, one self block per boundary face)."""
+    nt = int(mesh.cell_ptr[-1]) // 4
+    interior = int((mesh.face_cell[1::2] >= 0).sum())
+    boundary = mesh.n_faces - interior
+    vol = 2 * (3 * q_tet * nt) * nb * nb
+    face = (4 * interior + boundary) * 2 * (2 * q_tri) * nb * nb
+    return vol + face
+
+
+def roofline_hbm(abytes, kernel_ms, kernel, traffic=None):
+    achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel, "algorithmic_bytes": abytes}
+
+
+def hbm_copy_gbs(torch, mib=1024):
+    """Device-to-device copy of a mib-MiB buffer (read + write), the achievable HBM rate."""
+    x = torch.empty(mib * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        y.copy_(x)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 10
+    return 2 * x.numel() * 4 / (ms * 1e-3) / 1e9
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_rate(mesh, prob, parallel, budget_s):
+    """Median over passes (pattern + full assembly) of the oracle on the mesh."""
     import oracle
-    prob = oracle.Problem.from_params(params)
-    reps, t_total, nnzb = 0, 0.0, 0
-    while t_total < budget_s and reps < 200:
+    times, nnzb = [], 0
+    t_total = 0.0
+    while (t_total < budget_s or len(times) < 5) and len(times) < 200:
         t0 = time.perf_counter()
         pat = oracle.pattern(mesh)
-        oracle.assemble(mesh, prob, pat=pat)
-        t_total += time.perf_counter() - t0
+        oracle.assemble(mesh, prob, pat=pat, parallel=parallel)
+        dt = time.perf_counter() - t0
+        times.append(dt)
+        t_total += dt
         nnzb = pat.nnzb
-        reps += 1
-    return dict(value=nnzb * reps / t_total, unit="block-nnz/s", cores=1, kind="oracle",
-                sample=f"{reps} full passes (pattern + assembly) over the same 16,384-cell mesh, "
-                       f"{t_total:.1f} s, single thread",
-                elements_per_s=mesh.n_cells * reps / t_total)
+    med = sorted(times)[len(times) // 2]
+    return nnzb / med, mesh.n_cells / med, len(times), t_total
+
+
+def cpu_baseline(mesh, params, budget_s=8.0):
+    """The oracle as it stands (FP64 C) on the same mesh, pattern + full assembly,
+    median of the passes that fit in about budget_s seconds each: the OpenMP
+    build with rows over all the threads OpenMP is given (the headline figure),
+    and the single-threaded canonical build."""
+    import oracle
+    prob = oracle.Problem.from_params(params)
+    v_par, e_par, n_par, t_par = _oracle_rate(mesh, prob, True, budget_s)
+    v_one, e_one, n_one, t_one = _oracle_rate(mesh, prob, False, budget_s)
+    cores = oracle.threads(parallel=True)
+    return dict(value=v_par, unit="block-nnz/s", cores=cores, kind="oracle",
+                sample=f"median of {n_par} full passes (pattern + assembly) over the same 16,384-cell mesh, "
+                       f"{t_par:.1f} s, OpenMP over rows on {cores} threads",
+                elements_per_s=e_par, nproc=os.cpu_count(), cpu_model=_cpu_model(),
+                single_thread={"value": v_one, "elements_per_s": e_one, "cores": 1,
+                               "sample": f"median of {n_one} passes, {t_one:.1f} s"})
 
 
 TRAIN_SEED = 2007048815  # key of the training polygon stream
@@ -172,6 +249,8 @@ def reduced_rule_study(D, torch, steps, warmup, train_polygons, train_epochs):
                          "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])},
             "rules_network_init": net, "rules_template_init": tmpl,
             "assemble_ms": t, "assemble_kernel_ms": kern,
+            "roofline_plain": roofline_hbm(algorithmic_bytes(mesh, info, 4), kern["plain"],
+                                           "k_row2d<float,3,3,false,false,*>"),
             "kernel_speedup": kern["plain"] / kern["reduced"],
             "rulegen_ms": rulegen,
             "break_even_assemblies": (rulegen / gain) if gain > 0 else None}
@@ -201,10 +280,14 @@ def mixed_degree_study(D, torch, steps, warmup):
         ms_t = _replay_ms(ctx, D, torch, steps, warmup)
         ctx.run(params, prec, vals, rhs)
         asm_t = ctx.time_kernels(10)[1]
+        vb = 4 if prec == D.F32 else 8
         out[name] = {"ms_per_step": ms, "block_nnz_per_s": info.nnzb / (ms * 1e-3),
                      "kernel_ms": {"prep": prep_ms, "assemble": asm_ms},
                      "autotuned": {"launch_cfg_by_degree": choice[1 if prec == D.F32 else 0][1:],
-                                   "ms_per_step": ms_t, "assemble_kernel_ms": asm_t}}
+                                   "ms_per_step": ms_t, "assemble_kernel_ms": asm_t},
+                     "roofline": roofline_hbm(algorithmic_bytes(mesh, info, vb), asm_t,
+                                              f"k_row2d<{'float' if prec == D.F32 else 'double'},p,4,true,false,*> "
+                                              f"(one launch per degree, summed)")}
         del vals, rhs
     ctx.close()
     return out
@@ -232,8 +315,17 @@ def polyhedra_study(D, torch, steps, warmup):
         ms = _replay_ms(ctx, D, torch, steps, warmup)
         ctx.run(params, prec, vals, rhs)
         prep_ms, asm_ms = ctx.time_kernels(10)
+        vb = 4 if prec == D.F32 else 8
+        fl = flops_3d(mesh, info)
+        peak = 157.3 if prec == D.F32 else 78.6
+        tf = fl / (asm_ms * 1e-3) / 1e12
         out[name] = {"ms_per_step": ms, "block_nnz_per_s": info.nnzb / (ms * 1e-3),
-                     "kernel_ms": {"prep": prep_ms, "assemble": asm_ms}}
+                     "kernel_ms": {"prep": prep_ms, "assemble": asm_ms},
+                     "roofline": {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                                  "frac": tf / peak, "traffic": None, "algorithmic_flops": fl,
+                                  "kernel": "k_vol3d + k_face3d",
+                                  "hbm": roofline_hbm(algorithmic_bytes_3d(mesh, info, vb), asm_ms,
+                                                      "k_vol3d + k_face3d")}}
         del vals, rhs
     ctx.close()
     return out
@@ -301,7 +393,10 @@ def main():
     mesh = config_mesh(2)
     params = problem_params(2)
     ctx = D.Context(0)
-    ctx.upload(mesh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.upload(mesh)  # host checks + copy of the host arrays to the device
+    upload_ms = (time.perf_counter() - t0) * 1e3
     info = ctx.pattern()
     vals, rhs = ctx.outputs(D.F32)
 
@@ -350,6 +445,7 @@ def main():
     avg = {"prep": prep_ms, "assemble": asm_ms}
     abytes = algorithmic_bytes(mesh, info, 4)
     achieved = abytes / (avg["assemble"] * 1e-3) / 1e9
+    copy_gbs = hbm_copy_gbs(torch)
 
     out = {
         "metric": "assembled block-nnz/s, 2D Voronoi p=2 (whole path: geometry + pattern + assembly)",
@@ -375,7 +471,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg),
                      "kernel": f"k_row2d<float,2,2,false,true,{alt}>", "algorithmic_bytes": abytes,
+                     "measured_copy_gbs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "valu_issue": valu_issue(cfg, avg["assemble"])},
+        "upload_ms": upload_ms,
         "launch_config": {"cfg": cfg, "register_budget": "one more wave per SIMD" if alt else "default",
                           "row_order": "(degree, sub-triangles) bins" if cfg & 2 else "cell id"},
     }

@@ -31,15 +31,25 @@ T_VOLUME, T_INTERIOR, T_BOUNDARY, T_RHS, T_ALL = 1, 2, 4, 8, 15
 PEN_DIAMETER, PEN_COVERING = 0, 1
 
 
-def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so (plain -O2, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def _compile(target, extra, force):
+    if force or not os.path.exists(target) or os.path.getmtime(target) < max(
             os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "oracle.h"))):
-        tmp = _LIB + f".tmp{os.getpid()}"
+        tmp = target + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
-                               "-Wno-unused-parameter", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-Wno-unused-parameter", *extra, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, target)
+    return target
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (plain -O2, no fast-math, one thread:
+    the canonical oracle) and liboracle_omp.so (the same source with OpenMP:
+    rows assembled in parallel, for the CPU baseline on all host cores)."""
+    _compile(_LIB_OMP, ["-fopenmp"], force)
+    return _compile(_LIB, [], force)
 
 
 class _Mesh(C.Structure):
@@ -102,18 +112,37 @@ class Problem:
 
 
 _lib = None
+_lib_omp = None
 _keep = []
+
+
+def _load(path):
+    L = C.CDLL(path)
+    L.orc_nb.restype = C.c_int
+    L.orc_basis.restype = C.c_int
+    for fn in ("orc_geometry", "orc_pattern_sizes", "orc_pattern", "orc_assemble", "orc_threads"):
+        getattr(L, fn).restype = C.c_int
+    return L
 
 
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
-        _lib.orc_nb.restype = C.c_int
-        _lib.orc_basis.restype = C.c_int
-        for fn in ("orc_geometry", "orc_pattern_sizes", "orc_pattern", "orc_assemble"):
-            getattr(_lib, fn).restype = C.c_int
+        _lib = _load(build())
     return _lib
+
+
+def lib_omp():
+    """The OpenMP build (rows in parallel over OMP_NUM_THREADS threads)."""
+    global _lib_omp
+    if _lib_omp is None:
+        build()
+        _lib_omp = _load(_LIB_OMP)
+    return _lib_omp
+
+
+def threads(parallel: bool = False) -> int:
+    return (lib_omp() if parallel else lib()).orc_threads()
 
 
 def _ptr(a):
@@ -232,9 +261,10 @@ def pattern(mesh) -> Pattern:
     return Pattern(row_ptr, col_idx, val_ptr, dof_ptr)
 
 
-def assemble(mesh, problem: Problem, rows=None, pat: Pattern = None):
+def assemble(mesh, problem: Problem, rows=None, pat: Pattern = None, parallel: bool = False):
     """FP64 block-CSR values and right-hand side.  With ``rows`` only those block
-    rows are computed (the other entries stay NaN)."""
+    rows are computed (the other entries stay NaN).  ``parallel`` runs the
+    OpenMP build (the same arithmetic per row, rows spread over threads)."""
     pat = pat or pattern(mesh)
     ms, keep = _mesh_struct(mesh)
     vals = np.full(pat.n_vals, np.nan)
@@ -245,7 +275,8 @@ def assemble(mesh, problem: Problem, rows=None, pat: Pattern = None):
         rows = np.ascontiguousarray(rows, dtype=np.int64)
         rptr, nr = rows.ctypes.data, rows.shape[0]
     ps = problem._struct()
-    rc = lib().orc_assemble(C.byref(ms), C.byref(ps), C.byref(_rules_struct()),
+    L = lib_omp() if parallel else lib()
+    rc = L.orc_assemble(C.byref(ms), C.byref(ps), C.byref(_rules_struct()),
                             *[C.c_void_p(a.ctypes.data) for a in (pat.row_ptr, pat.col_idx, pat.val_ptr, pat.dof_ptr)],
                             C.c_void_p(rptr), C.c_int64(nr),
                             C.c_void_p(vals.ctypes.data), C.c_void_p(rhs.ctypes.data))

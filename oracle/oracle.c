@@ -9,6 +9,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI 3.14159265358979323846
 #define MAXP 6
@@ -643,6 +646,15 @@ static int assemble_row(const orc_mesh *m, const orc_problem *pr, const orc_rule
     return 0;
 }
 
+/* Threads the OpenMP build uses (1 in the plain build). */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int orc_assemble(const orc_mesh *m, const orc_problem *pr, const orc_rules *ru,
                  const int64_t *row_ptr, const int32_t *col_idx, const int64_t *val_ptr,
                  const int64_t *dof_ptr, const int64_t *rows, int64_t n_rows,
@@ -668,12 +680,27 @@ int orc_assemble(const orc_mesh *m, const orc_problem *pr, const orc_rules *ru,
         for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) need[col_idx[k]] = 1;
     }
     int rc = 0;
-    for (int64_t c = 0; c < m->n_cells && !rc; ++c)
-        if (need[c]) rc = cell_geometry(m, pr, ru, c, &geo[c]);
-    for (int64_t t = 0; t < nr && !rc; ++t) {
-        int64_t r = rows ? rows[t] : t;
-        rc = assemble_row(m, pr, ru, geo, row_ptr, col_idx, val_ptr, dof_ptr, r, vals, rhs);
+    /* Rows are independent (each writes only its own blocks and load), so the
+     * OpenMP build (liboracle_omp.so, the CPU baseline on all host cores)
+     * splits them over threads; the plain build runs them in order.  Both
+     * compute every row with the same arithmetic in the same order. */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : rc)
+#endif
+    for (int64_t c = 0; c < m->n_cells; ++c)
+        if (need[c]) rc |= cell_geometry(m, pr, ru, c, &geo[c]) != 0;
+    int err = 0; /* the most negative row status (0 if every row assembled) */
+    if (!rc) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) reduction(min : err)
+#endif
+        for (int64_t t = 0; t < nr; ++t) {
+            int64_t r = rows ? rows[t] : t;
+            int e = assemble_row(m, pr, ru, geo, row_ptr, col_idx, val_ptr, dof_ptr, r, vals, rhs);
+            if (e < err) err = e;
+        }
     }
+    rc = rc ? -2 : err;
     free(geo);
     free(need);
     return rc;

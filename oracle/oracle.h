@@ -108,6 +108,10 @@ int orc_assemble(const orc_mesh *m, const orc_problem *pr, const orc_rules *ru,
                  const int64_t *dof_ptr, const int64_t *rows, int64_t n_rows,
                  double *vals, double *rhs);
 
+/* Threads used by orc_assemble: 1 in the plain build; the OpenMP build
+ * (compiled with -fopenmp) assembles rows in parallel. */
+int orc_threads(void);
+
 /* Manufactured data at a point: u, f = -div(a grad u) + b.grad u + c u. */
 void orc_exact(const orc_problem *pr, int dim, const double *x, double *u, double *f);
 

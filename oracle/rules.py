@@ -55,8 +55,31 @@ def gauss_legendre01(n: int):
         dp = n * (x * p1 - p0) / (x * x - 1.0)
         xs[i] = x
         ws[i] = 2.0 / ((1.0 - x * x) * dp * dp)
+    # polish each root by Newton on P_n in 50-digit arithmetic (mpmath), then round once
+    import mpmath as mp
+    with mp.workdps(50):
+        for i in range(n):
+            x = mp.mpf(float(xs[i]))
+            for _ in range(6):
+                p0, p1 = mp.mpf(1), x
+                for k in range(2, n + 1):
+                    p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+                if n == 1:
+                    p0, p1 = mp.mpf(1), x
+                dp = n * (x * p1 - p0) / (x * x - 1)
+                x = x - p1 / dp
+            p0, p1 = mp.mpf(1), x
+            for k in range(2, n + 1):
+                p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+            if n == 1:
+                p0, p1 = mp.mpf(1), x
+            dp = n * (x * p1 - p0) / (x * x - 1)
+            xs[i] = float(x)
+            ws[i] = float(2 / ((1 - x * x) * dp * dp))
     order = np.argsort(xs)
-    return 0.5 * (xs[order] + 1.0), 0.5 * ws[order]
+    t = (xs[order] + 1.0) / 2
+    w = ws[order] / 2
+    return t, w
 
 
 # ---------------------------------------------------------------- exact moments
@@ -209,8 +232,89 @@ def _solve_symmetric(structure, guess, d, degree):
             xm[k] -= h
             J[:, k] = (resid(xp) - resid(xm)) / (2 * h)
         x = x - np.linalg.solve(J, r)
+    x = _polish_symmetric(structure, x, d, exps)
     pts, w = _assemble(structure, x, d)
     return pts, w
+
+
+def _polish_symmetric(structure, x, d, exps, dps=50):
+    """Newton on the same invariant equations in dps-digit arithmetic (mpmath),
+    with the exact means as targets; the parameters are then rounded once to
+    double, so the rule is the double rule nearest the exact one rather than
+    one limited by the rounding of a double-precision Newton iteration."""
+    import mpmath as mp
+    d1 = d + 1
+    with mp.workdps(dps):
+        es_poly = [_elem_sym(d1, k) for k in range(2, d1 + 1)]
+        target = []
+        for ex in exps:
+            poly = {tuple([0] * d1): Fraction(1)}
+            for e_k, p in zip(es_poly, ex):
+                for _ in range(p):
+                    poly = _poly_mul(poly, e_k)
+            s = Fraction(0)
+            for e, c in poly.items():
+                num = factorial(d)
+                for a in e:
+                    num *= factorial(a)
+                s += c * Fraction(num, factorial(sum(e) + d))
+            target.append(mp.mpf(s.numerator) / s.denominator)
+
+        def points(v):
+            pts, ws, i = [], [], 0
+            for kind in structure:
+                w = v[i]
+                i += 1
+                par = v[i:i + _NPARAM[kind]]
+                i += _NPARAM[kind]
+                half = mp.mpf(1) / 2
+                base = {"S3": lambda: [mp.mpf(1) / 3] * 3, "S4": lambda: [mp.mpf(1) / 4] * 4,
+                        "S21": lambda: [par[0], par[0], 1 - 2 * par[0]],
+                        "S31": lambda: [par[0]] * 3 + [1 - 3 * par[0]],
+                        "S22": lambda: [par[0], par[0], half - par[0], half - par[0]],
+                        "S111": lambda: [par[0], par[1], 1 - par[0] - par[1]]}[kind]()
+                # invariants are symmetric: one representative per orbit, times its size
+                size = len(_orbit_points(kind, [float(t) for t in par], d))
+                pts.append(base)
+                ws.append(w * size)
+            return pts, ws
+
+        def resid(v):
+            pts, ws = points(v)
+            out = []
+            for ex, t in zip(exps, target):
+                acc = mp.mpf(0)
+                for q, w in zip(pts, ws):
+                    val = w
+                    for k, p in zip(range(2, d1 + 1), ex):
+                        ek = mp.mpf(0)
+                        for idx in combinations(range(d1), k):
+                            prod = mp.mpf(1)
+                            for j in idx:
+                                prod *= q[j]
+                            ek += prod
+                        val *= ek ** p
+                    acc += val
+                out.append(acc - t)
+            return mp.matrix(out)
+
+        v = [mp.mpf(float(t)) for t in x]
+        for _ in range(6):
+            r = resid(v)
+            h = mp.mpf(10) ** (-dps // 2)
+            J = mp.matrix(len(r), len(v))
+            for k in range(len(v)):
+                vp, vm = list(v), list(v)
+                vp[k] += h
+                vm[k] -= h
+                col = (resid(vp) - resid(vm)) / (2 * h)
+                for j in range(len(r)):
+                    J[j, k] = col[j]
+            step = mp.lu_solve(J, r)
+            v = [v[k] - step[k] for k in range(len(v))]
+        if max(abs(t) for t in resid(v)) > mp.mpf(10) ** (-35):
+            raise RuntimeError("high-precision Newton did not converge")
+        return np.array([float(t) for t in v])
 
 
 # Starting guesses: the published Dunavant (triangle) and Keast (tetrahedron)

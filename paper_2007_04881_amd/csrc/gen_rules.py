@@ -13,7 +13,11 @@ and emitted as hex-float constants:
   Gauss-Newton to *all* Cartesian monomial moments x^a y^b (z^c) of the
   reference simplex up to the degree (exact values a! b! c! / (a+b+c+d)!),
   started from rounded published values (Dunavant for triangles, Keast for
-  the tetrahedron).
+  the tetrahedron), then polished by the same Gauss-Newton iteration in
+  60-digit arithmetic (mpmath) and rounded once to double precision, so that
+  each emitted rule is the nearest double rule to the exact one (moment
+  residuals at the rounding level of the data, not of the double-precision
+  fit).  The Gauss-Legendre nodes and weights are polished the same way.
 
 Run:  python gen_rules.py > rules_data.h
 """
@@ -46,6 +50,22 @@ def gauss_legendre(n):
     w = 2.0 / ((1.0 - x * x) * dp * dp)
     o = np.argsort(x)
     return 0.5 * (x[o] + 1.0), 0.5 * w[o]
+
+
+def gauss_legendre_mp(n, dps=60):
+    """The n-point rule on [0, 1] polished by Newton on P_n in dps-digit arithmetic."""
+    import mpmath as mp
+    t0, _ = gauss_legendre(n)
+    with mp.workdps(dps):
+        xs, ws = [], []
+        for t in t0:
+            x = mp.mpf(2) * mp.mpf(float(t)) - 1
+            for _ in range(8):
+                x = x - mp.legendre(n, x) / mp.diff(lambda z: mp.legendre(n, z), x)
+            dp = mp.diff(lambda z: mp.legendre(n, z), x)
+            xs.append((x + 1) / 2)
+            ws.append(1 / ((1 - x * x) * dp * dp))
+        return np.array([float(v) for v in xs]), np.array([float(v) for v in ws])
 
 
 def _orbit(kind, par, d):
@@ -124,7 +144,83 @@ def fit_rule(struct, guess, d, deg):
         x = x - np.linalg.lstsq(J, r, rcond=None)[0]
     if np.abs(resid(x)).max() > 1e-15:
         raise RuntimeError("rule fit did not converge")
+    x = _polish_mp(struct, x, d, ex)
     return _build(struct, x, d)
+
+
+def _orbit_mp(kind, par, d, mp):
+    if kind == "c":
+        base = [mp.mpf(1) / (d + 1)] * (d + 1)
+    elif kind == "a":
+        base = [par[0]] * d + [1 - d * par[0]]
+    elif kind == "ab":
+        base = [par[0], par[1], 1 - par[0] - par[1]]
+    elif kind == "bb":
+        base = [par[0], par[0], mp.mpf(1) / 2 - par[0], mp.mpf(1) / 2 - par[0]]
+    import itertools
+    # the same permutations, in the same order, as the double-precision orbits
+    out, seen = [], []
+    ref = _orbit(kind, [float(v) for v in par], d)
+    for q in ref:
+        for perm in itertools.permutations(range(d + 1)):
+            cand = [base[i] for i in perm]
+            if all(abs(float(c) - v) < 1e-9 for c, v in zip(cand, q)):
+                out.append(cand)
+                break
+    return out
+
+
+def _polish_mp(struct, x, d, ex, dps=60):
+    """Gauss-Newton on the same moment equations in dps-digit arithmetic."""
+    import mpmath as mp
+    from fractions import Fraction
+    with mp.workdps(dps):
+        ref = []
+        for e in ex:
+            num = 1
+            for k in e:
+                num *= factorial(k)
+            fr = Fraction(num * factorial(d), factorial(sum(e) + d))
+            ref.append(mp.mpf(fr.numerator) / fr.denominator)
+
+        def resid(xv):
+            rows, i = [], 0
+            pts, wts = [], []
+            for kind in struct:
+                w = xv[i]
+                par = xv[i + 1:i + 1 + _NP[kind]]
+                i += 1 + _NP[kind]
+                for q in _orbit_mp(kind, par, d, mp):
+                    pts.append(q)
+                    wts.append(w)
+            for e, rv in zip(ex, ref):
+                s = mp.mpf(0)
+                for q, w in zip(pts, wts):
+                    t = w
+                    for k, a in enumerate(e):
+                        t *= q[k + 1] ** a
+                    s += t
+                rows.append(s - rv)
+            return mp.matrix(rows)
+
+        xv = [mp.mpf(float(v)) for v in x]
+        for _ in range(6):
+            r = resid(xv)
+            h = mp.mpf(10) ** (-dps // 2)
+            J = mp.matrix(len(r), len(xv))
+            for k in range(len(xv)):
+                xp = list(xv)
+                xm = list(xv)
+                xp[k] += h
+                xm[k] -= h
+                col = (resid(xp) - resid(xm)) / (2 * h)
+                for j in range(len(r)):
+                    J[j, k] = col[j]
+            step = mp.lu_solve(J.T * J, J.T * r)
+            xv = [xv[k] - step[k] for k in range(len(xv))]
+        if max(abs(v) for v in resid(xv)) > mp.mpf(10) ** (-40):
+            raise RuntimeError("high-precision polish did not converge")
+        return np.array([float(v) for v in xv])
 
 
 TRI = {
@@ -148,7 +244,7 @@ def emit(out):
     w("#define DGP_GL_MAX 16\n")
     ts, ws, offs = [], [], [0]
     for n in range(1, 17):
-        t, wt = gauss_legendre(n)
+        t, wt = gauss_legendre_mp(n)
         ts.extend(t)
         ws.extend(wt)
         offs.append(len(ts))

@@ -210,3 +210,16 @@ def test_split_edges_change_nothing(p):
     vs, fs = oracle.assemble(split, prob, pat=ps)
     assert np.abs(va - vs).max() <= 1e-12 * np.abs(va).max()
     assert np.abs(fa - fs).max() <= 1e-12 * np.abs(fa).max()
+
+
+def test_openmp_build_is_the_same_oracle():
+    """The OpenMP build (rows over threads, for the all-core CPU baseline) gives
+    bit-identical values: every row is the same arithmetic in the same order."""
+    m = voronoi_mesh(400, 31, lloyd=1, p=1)
+    m = m.with_degrees(np.random.default_rng(2).integers(1, 5, m.n_cells))
+    prob = oracle.Problem(a0=1.0, a1=0.5, b=(1.0, 0.5, 0.0), c=1.0)
+    pat = oracle.pattern(m)
+    v1, r1 = oracle.assemble(m, prob, pat=pat)
+    v2, r2 = oracle.assemble(m, prob, pat=pat, parallel=True)
+    assert np.array_equal(v1, v2) and np.array_equal(r1, r2)
+    assert oracle.threads() == 1

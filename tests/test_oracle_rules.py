@@ -61,3 +61,21 @@ def test_tet_rule_exact():
                 exact = factorial(a) * factorial(b) * factorial(c) / factorial(a + b + c + 3)
                 worst = max(worst, abs(np.dot(w, x ** a * y ** b * z ** c) / 6.0 - exact) / exact)
     assert worst < 1e-14
+
+
+@pytest.mark.parametrize("deg", [4, 6, 8])
+def test_triangle_rule_exact_in_rational_arithmetic(deg):
+    """The rule as stored (doubles) against the exact moments, summed exactly
+    (Fractions): residuals at the rounding level of the data, so the rule is the
+    double rule nearest the exact one (a double-precision fit leaves ~1e-14)."""
+    from fractions import Fraction as Fr
+    bary, w = rules.triangle_rule(deg)
+    B = [[Fr(float(v)) for v in row] for row in bary]
+    W = [Fr(float(v)) for v in w]
+    worst = 0.0
+    for a in range(deg + 1):
+        for b in range(deg + 1 - a):
+            s = sum(wi * q[1] ** a * q[2] ** b for wi, q in zip(W, B))
+            exact = Fr(2 * factorial(a) * factorial(b), factorial(a + b + 2))
+            worst = max(worst, abs(float(s - exact)) / float(exact))
+    assert worst < 1e-15
