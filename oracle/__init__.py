@@ -120,7 +120,8 @@ def _load(path):
     L = C.CDLL(path)
     L.orc_nb.restype = C.c_int
     L.orc_basis.restype = C.c_int
-    for fn in ("orc_geometry", "orc_pattern_sizes", "orc_pattern", "orc_assemble", "orc_threads"):
+    for fn in ("orc_geometry", "orc_pattern_sizes", "orc_pattern", "orc_assemble", "orc_threads",
+               "orc_assemble_st"):
         getattr(L, fn).restype = C.c_int
     return L
 
@@ -299,3 +300,53 @@ def dense(mesh, pat: Pattern, vals):
             c0 = pat.dof_ptr[c]
             A[r0:r0 + nr, c0:c0 + ncol] = vals[pat.val_ptr[k]:pat.val_ptr[k + 1]].reshape(nr, ncol)
     return A
+
+
+# ------------------------------------------------------------ space-time slabs
+class _Slab(C.Structure):
+    _fields_ = [("t0", C.c_double), ("t1", C.c_double), ("tp0", C.c_double), ("tau1", C.c_double),
+                ("tau2", C.c_double), ("prev", C.c_void_p)]
+
+
+def pattern_st(mesh) -> Pattern:
+    """Block pattern of a space-time slab over a 2D mesh: the spatial blocks,
+    each n_b(p) x n_b(p') with the space-time count n_b = (p+1)(p+2)(p+3)/6."""
+    sp = pattern(mesh)
+    nb3 = lambda p: (p + 1) * (p + 2) * (p + 3) // 6
+    nbc = np.array([nb3(int(p)) for p in mesh.cell_p], dtype=np.int64)
+    rows = np.repeat(np.arange(mesh.n_cells), np.diff(sp.row_ptr))
+    sizes = nbc[rows] * nbc[sp.col_idx]
+    val_ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    dof_ptr = np.concatenate([[0], np.cumsum(nbc)]).astype(np.int64)
+    return Pattern(sp.row_ptr, sp.col_idx, val_ptr, dof_ptr)
+
+
+def assemble_st(mesh, problem: Problem, t0, t1, tau=(0.0, 0.0), prev=None, tp0=None, rows=None,
+                pat: Pattern = None, parallel: bool = False):
+    """FP64 matrix and load of the space-time slab (t0, t1] over a 2D mesh
+    (orc_assemble_st): u = u_s(x, y) (1 + tau[0] t + tau[1] t^2); prev = the
+    previous slab's coefficients (its time box [tp0, t0]) or None for the exact u(., t0)."""
+    pat = pat or pattern_st(mesh)
+    ms, keep = _mesh_struct(mesh)
+    vals = np.full(pat.n_vals, np.nan)
+    rhs = np.full(pat.n_dofs, np.nan)
+    sl = _Slab()
+    sl.t0, sl.t1, sl.tau1, sl.tau2 = t0, t1, tau[0], tau[1]
+    sl.tp0 = tp0 if tp0 is not None else t0 - (t1 - t0)
+    prev_arr = None
+    if prev is not None:
+        prev_arr = np.ascontiguousarray(prev, dtype=np.float64)
+        sl.prev = prev_arr.ctypes.data
+    if rows is None:
+        rptr, nr = None, 0
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        rptr, nr = rows.ctypes.data, rows.shape[0]
+    ps = problem._struct()
+    L = lib_omp() if parallel else lib()
+    rc = L.orc_assemble_st(C.byref(ms), C.byref(ps), C.byref(_rules_struct()), C.byref(sl),
+                           *[C.c_void_p(a.ctypes.data) for a in (pat.row_ptr, pat.col_idx, pat.val_ptr, pat.dof_ptr)],
+                           C.c_void_p(rptr), C.c_int64(nr), C.c_void_p(vals.ctypes.data), C.c_void_p(rhs.ctypes.data))
+    if rc:
+        raise ValueError(f"orc_assemble_st failed ({rc})")
+    return vals, rhs

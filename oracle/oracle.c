@@ -705,3 +705,205 @@ int orc_assemble(const orc_mesh *m, const orc_problem *pr, const orc_rules *ru,
     free(need);
     return rc;
 }
+
+/* ------------------------------------------------------------ space-time */
+/* u = u_s T, T(t) = 1 + tau1 t + tau2 t^2; grad u = T grad u_s; f = u_s T' + T f_s */
+static void st_exact(const orc_problem *pr, const orc_slab *sl, const double *x, double t, double *u, double *gu,
+                     double *f) {
+    double us, gus[3], lap, fs;
+    exact_u(pr, 2, x, &us, gus, &lap);
+    orc_exact(pr, 2, x, &us, &fs);
+    double T = 1.0 + sl->tau1 * t + sl->tau2 * t * t, dT = sl->tau1 + 2.0 * sl->tau2 * t;
+    *u = us * T;
+    if (gu) {
+        gu[0] = T * gus[0];
+        gu[1] = T * gus[1];
+    }
+    if (f) *f = us * dT + T * fs;
+}
+
+/* Row r of the slab: the volume terms (time derivative, diffusion, advection,
+ * reaction) on the prism, the time-jump term on its bottom, the face terms on
+ * the space-time faces I_n x F, and the load. */
+static int assemble_row_st(const orc_mesh *m, const orc_problem *pr, const orc_rules *ru, const orc_slab *sl,
+                           const cellgeo *geo, const int64_t *row_ptr, const int32_t *col_idx,
+                           const int64_t *val_ptr, const int64_t *dof_ptr, int64_t r, double *vals, double *rhs) {
+    const int pr_ = m->cell_p[r];
+    const int nbr = orc_nb(3, pr_);
+    const cellgeo *gr = &geo[r];
+    const double tau = sl->t1 - sl->t0;
+    int64_t k0 = row_ptr[r], k1 = row_ptr[r + 1], kd = -1;
+    for (int64_t k = k0; k < k1; ++k)
+        if (col_idx[k] == r) kd = k;
+    if (kd < 0) return -2;
+    for (int64_t v = val_ptr[k0]; v < val_ptr[k1]; ++v) vals[v] = 0.0;
+    double *F = rhs + dof_ptr[r];
+    for (int i = 0; i < nbr; ++i) F[i] = 0.0;
+    double *D = vals + val_ptr[kd];
+    double lo[3] = {gr->lo[0], gr->lo[1], sl->t0}, hi[3] = {gr->hi[0], gr->hi[1], sl->t1};
+    double phi[MAXNB], grad[MAXNB * 3], phio[MAXNB], grado[MAXNB * 3];
+    /* Gauss in time with p + 1 points: exact for the degree-2p products */
+    const orc_rule *gt = &ru->seg[pr_ + 1];
+
+    double *X = NULL, *W = NULL;
+    int64_t nq = vol_points(m, ru, r, pr_, &X, &W);
+    if (nq < 0) return (int)nq;
+    for (int64_t q = 0; q < nq; ++q) {
+        for (int k = 0; k < gt->n; ++k) {
+            double t = sl->t0 + gt->pts[k] * tau;
+            double w = W[q] * gt->w[k] * tau;
+            double x3[3] = {X[3 * q], X[3 * q + 1], t};
+            orc_basis(3, pr_, lo, hi, x3, phi, grad);
+            double a = coef_a(pr, X + 3 * q), u, f;
+            st_exact(pr, sl, X + 3 * q, t, &u, NULL, &f);
+            for (int i = 0; i < nbr; ++i) {
+                for (int j = 0; j < nbr; ++j) {
+                    double gg = grad[3 * j] * grad[3 * i] + grad[3 * j + 1] * grad[3 * i + 1];
+                    double bg = pr->b[0] * grad[3 * j] + pr->b[1] * grad[3 * j + 1];
+                    D[i * nbr + j] += w * (grad[3 * j + 2] * phi[i] + a * gg + bg * phi[i] + pr->c * phi[j] * phi[i]);
+                }
+                F[i] += w * f * phi[i];
+            }
+        }
+    }
+    /* time jump at t0: (U^+, W^+) on the matrix side, (U^-_{n-1}, W^+) on the load side */
+    for (int64_t q = 0; q < nq; ++q) {
+        double x3[3] = {X[3 * q], X[3 * q + 1], sl->t0};
+        orc_basis(3, pr_, lo, hi, x3, phi, grad);
+        double uprev;
+        if (sl->prev) {
+            double plo[3] = {gr->lo[0], gr->lo[1], sl->tp0}, phi_[3] = {gr->hi[0], gr->hi[1], sl->t0};
+            orc_basis(3, pr_, plo, phi_, x3, phio, grado);
+            uprev = 0.0;
+            for (int j = 0; j < nbr; ++j) uprev += sl->prev[dof_ptr[r] + j] * phio[j];
+        } else {
+            st_exact(pr, sl, X + 3 * q, sl->t0, &uprev, NULL, NULL);
+        }
+        for (int i = 0; i < nbr; ++i) {
+            for (int j = 0; j < nbr; ++j) D[i * nbr + j] += W[q] * phi[j] * phi[i];
+            F[i] += W[q] * uprev * phi[i];
+        }
+    }
+    free(X);
+    free(W);
+
+    const double hst_r = sqrt(gr->diam * gr->diam + tau * tau);
+    facepts fp;
+    for (int64_t kf = m->cell_face_ptr[r]; kf < m->cell_face_ptr[r + 1]; ++kf) {
+        int32_t f = m->cell_face[kf];
+        int32_t lft = m->face_cell[2 * f], rgt = m->face_cell[2 * f + 1];
+        if (lft != r && rgt != r) return -2;
+        int32_t o = (lft == r) ? rgt : lft;
+        int po = o >= 0 ? m->cell_p[o] : -1;
+        int pmax = po > pr_ ? po : pr_;
+        int rc = face_points(m, ru, f, r, pmax, gr, &fp);
+        if (rc) return rc;
+        const double *n = fp.n;
+        double bn = pr->b[0] * n[0] + pr->b[1] * n[1];
+        double sigma;
+        if (pr->sigma_override >= 0) {
+            sigma = pr->sigma_override;
+        } else {
+            double s1 = gr->abar * pr_ * pr_ / hst_r, s2 = 0.0;
+            if (o >= 0) {
+                double hso = sqrt(geo[o].diam * geo[o].diam + tau * tau);
+                s2 = geo[o].abar * po * po / hso;
+            }
+            sigma = pr->c_sigma * (s1 > s2 ? s1 : s2);
+        }
+        int nbo = o >= 0 ? orc_nb(3, po) : 0;
+        double *C = NULL;
+        double olo[3] = {0, 0, 0}, ohi[3] = {0, 0, 0};
+        if (o >= 0) {
+            for (int64_t kk = k0; kk < k1; ++kk)
+                if (col_idx[kk] == o) C = vals + val_ptr[kk];
+            if (!C) return -2;
+            olo[0] = geo[o].lo[0], olo[1] = geo[o].lo[1], olo[2] = sl->t0;
+            ohi[0] = geo[o].hi[0], ohi[1] = geo[o].hi[1], ohi[2] = sl->t1;
+        }
+        for (int q = 0; q < fp.npts; ++q) {
+            for (int k = 0; k < gt->n; ++k) {
+                double t = sl->t0 + gt->pts[k] * tau;
+                double w = fp.W[q] * gt->w[k] * tau;
+                double x3[3] = {fp.X[3 * q], fp.X[3 * q + 1], t};
+                orc_basis(3, pr_, lo, hi, x3, phi, grad);
+                double a = coef_a(pr, fp.X + 3 * q);
+                int up = bn < 0.0;
+                if (o >= 0) {
+                    orc_basis(3, po, olo, ohi, x3, phio, grado);
+                    for (int i = 0; i < nbr; ++i) {
+                        double dni = grad[3 * i] * n[0] + grad[3 * i + 1] * n[1];
+                        for (int j = 0; j < nbr; ++j) {
+                            double dnj = grad[3 * j] * n[0] + grad[3 * j + 1] * n[1];
+                            double s = -0.5 * a * dnj * phi[i] - 0.5 * a * dni * phi[j] + sigma * phi[j] * phi[i];
+                            if (up) s -= bn * phi[j] * phi[i];
+                            D[i * nbr + j] += w * s;
+                        }
+                        for (int j = 0; j < nbo; ++j) {
+                            double dnj = grado[3 * j] * n[0] + grado[3 * j + 1] * n[1];
+                            double s = -0.5 * a * dnj * phi[i] + 0.5 * a * dni * phio[j] - sigma * phio[j] * phi[i];
+                            if (up) s += bn * phio[j] * phi[i];
+                            C[i * nbo + j] += w * s;
+                        }
+                    }
+                } else if (m->face_bc[f] == 1) {
+                    double g, gu[2];
+                    st_exact(pr, sl, fp.X + 3 * q, t, &g, gu, NULL);
+                    for (int i = 0; i < nbr; ++i) {
+                        double dni = grad[3 * i] * n[0] + grad[3 * i + 1] * n[1];
+                        for (int j = 0; j < nbr; ++j) {
+                            double dnj = grad[3 * j] * n[0] + grad[3 * j + 1] * n[1];
+                            double s = -a * dnj * phi[i] - a * dni * phi[j] + sigma * phi[j] * phi[i];
+                            if (up) s -= bn * phi[j] * phi[i];
+                            D[i * nbr + j] += w * s;
+                        }
+                        double s = -g * a * dni + sigma * g * phi[i];
+                        if (up) s -= bn * g * phi[i];
+                        F[i] += w * s;
+                    }
+                } else if (m->face_bc[f] == 2) {
+                    double g, gu[2];
+                    st_exact(pr, sl, fp.X + 3 * q, t, &g, gu, NULL);
+                    double gN = a * (gu[0] * n[0] + gu[1] * n[1]);
+                    for (int i = 0; i < nbr; ++i) F[i] += w * gN * phi[i];
+                } else {
+                    return -2;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+int orc_assemble_st(const orc_mesh *m, const orc_problem *pr, const orc_rules *ru, const orc_slab *sl,
+                    const int64_t *row_ptr, const int32_t *col_idx, const int64_t *val_ptr,
+                    const int64_t *dof_ptr, const int64_t *rows, int64_t n_rows, double *vals, double *rhs) {
+    if (!m || !pr || !ru || !sl || m->dim != 2 || m->n_cells <= 0 || !(sl->t1 > sl->t0)) return -1;
+    if (pr->penalty != ORC_PEN_DIAMETER) return -3;
+    if (sl->prev && !(sl->t0 > sl->tp0)) return -1;
+    leg_init();
+    for (int64_t c = 0; c < m->n_cells; ++c)
+        if (m->cell_p[c] < 1 || m->cell_p[c] > 4) return -3;
+    const int64_t ncell = m->n_cells;
+    if (ncell > ((int64_t)1 << 31)) return -1;
+    cellgeo *geo = (cellgeo *)calloc((size_t)ncell, sizeof(cellgeo));
+    if (!geo) return -1;
+    int rc = 0;
+    for (int64_t c = 0; c < ncell && !rc; ++c) rc = cell_geometry(m, pr, ru, c, &geo[c]);
+    int64_t nr = rows ? n_rows : ncell;
+    int err = 0;
+    if (!rc) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) reduction(min : err)
+#endif
+        for (int64_t t = 0; t < nr; ++t) {
+            int64_t r = rows ? rows[t] : t;
+            int e = (r < 0 || r >= m->n_cells) ? -1
+                                                : assemble_row_st(m, pr, ru, sl, geo, row_ptr, col_idx, val_ptr,
+                                                                  dof_ptr, r, vals, rhs);
+            if (e < err) err = e;
+        }
+    }
+    free(geo);
+    return rc ? rc : err;
+}

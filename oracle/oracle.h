@@ -108,6 +108,27 @@ int orc_assemble(const orc_mesh *m, const orc_problem *pr, const orc_rules *ru,
                  const int64_t *dof_ptr, const int64_t *rows, int64_t n_rows,
                  double *vals, double *rhs);
 
+/* Space-time slab I_n = (t0, t1] over a 2D mesh (Section 2.3, equation
+ * spacetime_dg): prisms I_n x kappa with the total-degree-p space-time basis on
+ * the box [lo_x, hi_x] x [lo_y, hi_y] x [t0, t1] (the 3D basis with t as the
+ * third coordinate, n_b = (p+1)(p+2)(p+3)/6; blocks laid out as for a 3D
+ * mesh).  The manufactured solution is u(x, y, t) = u_s(x, y) T(t), u_s as in
+ * orc_problem, T = 1 + tau1 t + tau2 t^2, so f = u_s T' + T f_s.  The time jump
+ * takes U_{n-1}^- from prev (the previous slab's coefficients on the box in
+ * time [tp0, t0], same degrees and dof layout) or, if prev is NULL, the exact
+ * u(., t0). */
+typedef struct {
+    double t0, t1, tp0;
+    double tau1, tau2;
+    const double *prev;
+} orc_slab;
+
+/* Rows of the slab system (diameter penalty with h = the prism's diameter;
+ * the covering penalty is not defined here: -3). */
+int orc_assemble_st(const orc_mesh *m, const orc_problem *pr, const orc_rules *ru, const orc_slab *sl,
+                    const int64_t *row_ptr, const int32_t *col_idx, const int64_t *val_ptr,
+                    const int64_t *dof_ptr, const int64_t *rows, int64_t n_rows, double *vals, double *rhs);
+
 /* Threads used by orc_assemble: 1 in the plain build; the OpenMP build
  * (compiled with -fopenmp) assembles rows in parallel. */
 int orc_threads(void);
