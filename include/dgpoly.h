@@ -186,6 +186,24 @@ dgp_status dgp_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, in
  * (sizes known).  Asynchronous; no host synchronisation. */
 dgp_status dgp_run(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode, void *vals, void *rhs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): dgp_run with the
+ * step's scratch (the preparation outputs: element records, edge or face
+ * records, row counts, tile sums) in a static device array of
+ * DGP_STATIC_SCRATCH_BYTES that the library holds on every device it runs on,
+ * instead of the buffer the context allocates at upload.  Same arguments,
+ * results bit-identical to dgp_run; the call itself allocates and frees
+ * nothing.  Fails with DGP_EUNSUPPORTED if the mesh needs more scratch than
+ * the array holds (2D: 64 B per element, 36 B per loop edge, 16 B per element
+ * of row counts, 40 B per tile of 32 elements).  All calls on one device share
+ * that device's array: calls that overlap on one device (several streams or
+ * contexts, host threads) race and must be serialised by the caller.
+ * Asynchronous.  Afterwards dgp_time_kernels and dgp_autotune report
+ * DGP_ESTATE until the next dgp_run or dgp_assemble. */
+#define DGP_STATIC_SCRATCH_BYTES (64u << 20)
+dgp_status dgp_run_static(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode, void *vals,
+                          void *rhs);
+
 /* Capture dgp_run (what = 0) or dgp_assemble (what = 1) with these arguments
  * into a HIP graph held by the context, and replay it. */
 dgp_status dgp_graph_capture(dgp_ctx *ctx, int what, const dgp_problem *prob, int precision, int rule_mode,

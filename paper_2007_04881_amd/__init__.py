@@ -69,7 +69,7 @@ class TrainStats(C.Structure):
 
 
 EXPORTS = ["dgp_create", "dgp_destroy", "dgp_set_stream", "dgp_last_error", "dgp_mesh_check", "dgp_mesh_upload", "dgp_pattern",
-           "dgp_pattern_copy", "dgp_assemble", "dgp_run", "dgp_graph_capture", "dgp_graph_launch",
+           "dgp_pattern_copy", "dgp_assemble", "dgp_run", "dgp_run_static", "dgp_graph_capture", "dgp_graph_launch",
            "dgp_set_timing", "dgp_kernel_ms", "dgp_time_kernels", "dgp_autotune", "dgp_set_launch", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
            "dgp_qrule_cell_data", "dgp_train_polygons", "dgp_mlp_forward", "dgp_mlp_loss_grad", "dgp_adam_step",
            "dgp_mlp_train"]
@@ -97,7 +97,7 @@ def lib():
         L.dgp_mesh_upload.argtypes = [C.c_void_p, C.POINTER(MeshDesc)]
         L.dgp_pattern.argtypes = [C.c_void_p, C.POINTER(PatternInfo)]
         L.dgp_pattern_copy.argtypes = [C.c_void_p] + [C.c_void_p] * 4
-        for name in ("dgp_assemble", "dgp_run"):
+        for name in ("dgp_assemble", "dgp_run", "dgp_run_static"):
             getattr(L, name).argtypes = [C.c_void_p, C.POINTER(ProblemDesc), C.c_int, C.c_int, C.c_void_p,
                                          C.c_void_p]
         L.dgp_graph_capture.argtypes = [C.c_void_p, C.c_int, C.POINTER(ProblemDesc), C.c_int, C.c_int,
@@ -262,6 +262,13 @@ class Context:
         pd = problem_desc(problem)
         self._check(lib().dgp_run(self._h, C.byref(pd), precision, rule_mode, vals.data_ptr(), rhs.data_ptr()),
                     "dgp_run")
+
+    def run_static(self, problem: dict, precision, vals, rhs, rule_mode=RULE_PLAIN):
+        """dgp_run with the step's scratch in the library's static device array (allocates nothing)."""
+        self._tensors_ok(vals, rhs, precision)
+        pd = problem_desc(problem)
+        self._check(lib().dgp_run_static(self._h, C.byref(pd), precision, rule_mode, vals.data_ptr(),
+                                         rhs.data_ptr()), "dgp_run_static")
 
     def graph_capture(self, what, problem: dict, precision, vals, rhs, rule_mode=RULE_PLAIN):
         self._tensors_ok(vals, rhs, precision)

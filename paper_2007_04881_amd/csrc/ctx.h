@@ -42,6 +42,8 @@ struct dgp_ctx {
     int n_tiles = 0;
 
 
+    void *static_scratch = nullptr;  // device address of the library's static scratch array on this device
+
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -71,6 +72,38 @@ static dgp_status upload(dgp_ctx *c, const T *src, int64_t n, const T **dst) {
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ---- static scratch of dgp_run_static
+// The preparation outputs of a step taken by dgp_run_static live in this
+// array instead of the buffer the context allocates at upload.  Each device
+// the library runs on holds its own copy for the life of the process.  In host
+// code `scratch` only names the symbol: its device address, per device, comes
+// from hipGetSymbolAddress at context creation and is the only address that
+// host code passes on.
+static __device__ __align__(256) unsigned char scratch[DGP_STATIC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device` (looked up once per device).
+static hipError_t static_scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = ptr;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 
 // The preparation outputs of one step (2D: per-face penalty sides, cell
 // records, edge neighbours and records, row counts, tile sums and offsets)
@@ -140,6 +173,13 @@ dgp_status dgp_create(dgp_ctx **out, int device, void *hip_stream) {
             return DGP_EDEVICE;
         }
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return DGP_EDEVICE;
+    }
+    if (static_scratch_address(device, &c->static_scratch) != hipSuccess) {
+        (void)hipStreamDestroy(c->cap_stream);
+        for (auto &e : c->ev)
+            if (e) (void)hipEventDestroy(e);
         delete c;
         return DGP_EDEVICE;
     }
@@ -742,6 +782,41 @@ dgp_status dgp_run(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rul
     if (st) return st;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     return enqueue_assemble(ctx, prob, precision, rule_mode, 1, vals, rhs, ctx->stream, ctx->timing);
+}
+
+dgp_status dgp_run_static(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode, void *vals,
+                          void *rhs) {
+    dgp_status st = check_assemble_args(ctx, prob, precision, rule_mode, vals, rhs);
+    if (st) return st;
+    if (!ctx->static_scratch) return fail(ctx, DGP_ESTATE, "no static scratch address for device %d", ctx->device);
+    const size_t need = ctx->dim == 3 ? layout3d(ctx->n_cells, ctx->n_cell_face, ctx->n_tiles, nullptr, nullptr)
+                                      : layout2d(ctx->n_cells, ctx->n_cell_vtx, ctx->n_faces, ctx->n_tiles, nullptr,
+                                                 nullptr);
+    if (need > (size_t)DGP_STATIC_SCRATCH_BYTES)
+        return fail(ctx, DGP_EUNSUPPORTED,
+                    "dgp_run_static: this mesh needs %zu bytes of scratch, the static array holds %zu", need,
+                    (size_t)DGP_STATIC_SCRATCH_BYTES);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    char *base = static_cast<char *>(ctx->static_scratch);
+    // the step runs with the context's preparation outputs moved into the static array
+    const PrepOut own2 = ctx->prep;
+    const Prep3Out own3 = ctx->prep3;
+    if (ctx->dim == 3) {
+        layout3d(ctx->n_cells, ctx->n_cell_face, ctx->n_tiles, base, &ctx->prep3);
+        // the limit flag is only ever raised by the preparation kernel: clear the
+        // previous call's value (a kernel, not a memset node, so that the call can
+        // be captured into a graph)
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, ctx->stream, ctx->prep3.err, 1, 0);
+    } else {
+        layout2d(ctx->n_cells, ctx->n_cell_vtx, ctx->n_faces, ctx->n_tiles, base, &ctx->prep);
+    }
+    st = enqueue_assemble(ctx, prob, precision, rule_mode, 1, vals, rhs, ctx->stream, ctx->timing);
+    ctx->prep = own2;
+    ctx->prep3 = own3;
+    // dgp_time_kernels and dgp_autotune re-launch the last step on the
+    // context's own buffers, which this step did not fill
+    ctx->has_last = false;
+    return st;
 }
 
 dgp_status dgp_graph_capture(dgp_ctx *ctx, int what, const dgp_problem *prob, int precision, int rule_mode,
