@@ -331,6 +331,76 @@ def polyhedra_study(D, torch, steps, warmup):
     return out
 
 
+def approach1_study(D, torch, steps, warmup):
+    """Approach 1 of Section 3.3 (COO records with duplicates, radix sort,
+    segmented sums) against the pattern-first row-owner path on the 16,384-cell
+    FP32 workload: device time per whole assembly, pattern included."""
+    from meshgen import config_mesh, problem_params
+    log("Approach 1 ablation: 16,384-cell mesh")
+    mesh, params = config_mesh(2), problem_params(2)
+    ctx = D.Context(0)
+    ctx.upload(mesh)
+    info = ctx.pattern()
+    out = {}
+    ctx.assemble_coo(params, D.F32)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        ctx.assemble_coo(params, D.F32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.assemble_coo(params, D.F32)
+    torch.cuda.synchronize()
+    a1 = (time.perf_counter() - t0) * 1e3 / steps
+    vals, rhs = ctx.outputs(D.F32)
+    for _ in range(warmup):
+        ctx.run(params, D.F32, vals, rhs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run(params, D.F32, vals, rhs)
+    torch.cuda.synchronize()
+    a2 = (time.perf_counter() - t0) * 1e3 / steps
+    ctx.close()
+    records = mesh.n_cells + 4 * mesh.n_faces
+    return {"workload": "2D DAR, 16384-cell seeded Voronoi, p=2, FP32", "nnzb": info.nnzb, "coo_records": records,
+            "approach1_ms_per_step": a1, "approach2_ms_per_step": a2, "approach2_speedup": a1 / a2,
+            "approach1_block_nnz_per_s": info.nnzb / (a1 * 1e-3)}
+
+
+def spacetime_study(D, torch, steps, warmup):
+    """One space-time slab (Section 2.3) of the parabolic benchmark's kind (a = 1,
+    w = 0, c = 1) on prisms over the 16,384-cell Voronoi mesh, p = 1..3, FP64
+    and FP32: device time per slab, block nonzeros and seconds per million
+    degrees of freedom (the unit of the paper's tables)."""
+    from meshgen import voronoi_mesh
+    log("space-time slabs: 16,384 prisms")
+    heat = dict(a0=1.0, a1=0.0, b=(0.0, 0.0, 0.0), c=1.0, c_sigma=10.0, u="sin")
+    out = {"workload": "space-time slab, prisms over a 16384-cell seeded Voronoi mesh, a=1, w=0, c=1"}
+    for p in (1, 2, 3):
+        mesh = voronoi_mesh(16384, 2007048812, lloyd=0, p=p)
+        ctx = D.Context(0)
+        ctx.upload(mesh)
+        info = ctx.pattern()
+        nb = (p + 1) * (p + 2) * (p + 3) // 6
+        for prec, name in ((D.F64, "f64"), (D.F32, "f32")):
+            outs = ctx.assemble_st(heat, prec, 0.0, 0.01)
+            for _ in range(warmup):
+                ctx.assemble_st(heat, prec, 0.0, 0.01, out=outs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.assemble_st(heat, prec, 0.0, 0.01, out=outs)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            mdof = mesh.n_cells * nb / 1e6
+            out[f"p{p}_{name}"] = {"ms_per_slab": ms, "dofs": mesh.n_cells * nb,
+                                   "block_nnz_per_s": info.nnzb / (ms * 1e-3), "s_per_mdof": ms * 1e-3 / mdof}
+            del outs
+        ctx.close()
+    return out
+
+
 def traffic_probe(D, torch):
     """A short program for rocprofv3 --pmc: the assembly kernel's dispatches and
     a copy of known size to scale the counters by."""
@@ -368,6 +438,7 @@ def main():
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-rule study")
     ap.add_argument("--no-3d", action="store_true", help="skip the polyhedral (3D) workload")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree 262,144-cell workload")
+    ap.add_argument("--no-extras", action="store_true", help="skip the Approach-1 and space-time studies")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for HBM counter runs: 10 whole steps of the headline workload, 10 more in each of the "
                          "four launch configurations, then 10 copies of a "
@@ -484,6 +555,9 @@ def main():
         out["mixed_degrees"] = mixed_degree_study(D, torch, 20, 3)
     if not args.no_3d:
         out["polyhedra"] = polyhedra_study(D, torch, 20, 3)
+    if not args.no_extras:
+        out["approach1"] = approach1_study(D, torch, 20, 3)
+        out["spacetime"] = spacetime_study(D, torch, 10, 2)
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mesh, params)

@@ -235,15 +235,61 @@ dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assem
  * degree.  Results do not depend on the configuration.  Values of the last
  * call's output buffers are rewritten (they must still be allocated).  3D
  * meshes and reduced rules have a single configuration (nothing changes).
- * choice: NULL or int32[2][5], cfg in use per [FP64, FP32][degree 0..4] on
- * return.  Synchronous.  DGP_EINVAL if budget_ms < 1, DGP_ESTATE before an
- * assembly. */
+ * Configurations whose larger occupancy makes the kernel spill more registers
+ * than the default are not tried.  On a mesh of mixed degrees the tuned
+ * per-degree launches are then timed against one persistent launch over all
+ * bins and the faster is kept.  choice: NULL or int32[2][5], per [FP64, FP32]:
+ * entry 0 = 1 if mixed degrees take the single launch, entries 1..4 = the cfg
+ * of each degree.  Synchronous.  DGP_EINVAL if budget_ms < 1, DGP_ESTATE
+ * before an assembly. */
 dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice);
 
 /* Set the 2D launch configuration cfg (0..3, as for dgp_autotune) of one
- * precision and degree without timing, for reproducible launches.
- * DGP_EINVAL for a bad precision or cfg, DGP_EUNSUPPORTED for p outside 1..4. */
+ * precision and degree without timing, for reproducible launches; p = 0 sets
+ * how meshes of mixed degree are launched: cfg 0 one launch per degree, cfg 1
+ * one persistent launch over every (degree, sub-triangle count) bin, the
+ * costliest bins first (the same per-row arithmetic: bit-identical results).
+ * DGP_EINVAL for a bad precision or cfg, DGP_EUNSUPPORTED for p outside 0..4. */
 dgp_status dgp_set_launch(dgp_ctx *ctx, int precision, int p, int cfg);
+
+/* Approach 1 of Section 3.3, as an ablation of the pattern-first assembly:
+ * every element and every face computes its local blocks on its own and emits
+ * them as COO records with duplicates (element: its block and load; interior
+ * face: four blocks; boundary face: one block and its load); a stable radix
+ * sort of the records by (row, column) and a segmented reduction (each block
+ * summed over its records in sorted order) then produce the block pattern and
+ * the values.  Outputs are caller-owned device buffers of the sizes dgp_pattern
+ * reports (required first; its arrays are not used): row_ptr[n_rows+1],
+ * col_idx[nnzb], val_ptr[nnzb+1], dof_ptr[n_rows+1], vals[n_vals], rhs[n_dofs].
+ * 2D meshes of one degree (DGP_EUNSUPPORTED otherwise); either penalty.  The
+ * first call allocates the record and sort workspace (about (n_cells + 4 n_faces)
+ * (n_b^2 + n_b) doubles), kept by the context.  Asynchronous. */
+dgp_status dgp_assemble_coo(dgp_ctx *ctx, const dgp_problem *prob, int precision, void *vals, void *rhs,
+                            int64_t *row_ptr, int32_t *col_idx, int64_t *val_ptr, int64_t *dof_ptr);
+
+/* One time slab I_n = (t0, t1] of the space-time method of Section 2.3
+ * (equation spacetime_dg) on prisms I_n x kappa over the uploaded 2D mesh. */
+typedef struct {
+    double t0, t1;       /* the slab, t1 > t0 */
+    double tp0;          /* start of the previous slab (its box in time is [tp0, t0]); used with prev */
+    double tau1, tau2;   /* manufactured u(x, y, t) = u_s(x, y) (1 + tau1 t + tau2 t^2), u_s from dgp_problem */
+    const double *prev;  /* device: the previous slab's coefficients [n_cells][n_b] (FP64), or NULL to take
+                            U_{n-1}^- = u(., t0) */
+} dgp_slab;
+
+/* Matrix and load of one slab: the basis of total degree p in (x, y, t) on each
+ * prism's box [lo, hi] x [t0, t1] (n_b = (p+1)(p+2)(p+3)/6, same order as the
+ * 3D basis with t as the third coordinate); volume terms with the time
+ * derivative, the time jump (U^+, W^+) on the prism's bottom and
+ * (U_{n-1}^-, W^+) in the load, the SIPG face terms on I_n x F (penalty
+ * C_sigma max abar p^2 / h with h the prism's diameter), the load with
+ * f = u_s T' + T f_s.  Quadrature: the fan rule x (p + 1) Gauss points in time;
+ * edge Gauss points x time Gauss points on the faces.  Block pattern: that of
+ * dgp_pattern (required first), blocks n_b x n_b: vals[nnzb n_b^2],
+ * rhs[n_cells n_b].  2D meshes of one degree p = 1..3, diameter penalty
+ * (DGP_EUNSUPPORTED otherwise).  Asynchronous. */
+dgp_status dgp_assemble_st(dgp_ctx *ctx, const dgp_problem *prob, int precision, const dgp_slab *slab, void *vals,
+                           void *rhs);
 
 /* ---------------------------------------------------------------------
  * Reduced volume rules for polygons (an extension of Section 3: the paper
@@ -265,6 +311,11 @@ typedef struct {
     int64_t iters_hist[16];      /* accepted elements by refinement steps taken (15 = 15 or more) */
     double max_residual_accepted;
     float ms_features, ms_network, ms_refine; /* device time of the three stages */
+    /* DGP_INIT_NETWORK: eligible elements that started from the network's rule
+     * (the others from the template, whose initial residual was smaller), and
+     * elements refined again from the template after a rejected network start,
+     * with how many of those were accepted */
+    int64_t n_start_network, n_retried, n_retry_accepted;
 } dgp_qrule_stats;
 
 typedef struct {
@@ -287,7 +338,11 @@ dgp_status dgp_mlp_load(dgp_ctx *ctx, const float *params, int64_t n_params);
 /* Build a rule for every element of the uploaded mesh (requires dgp_pattern):
  * element data, initial rule (init = DGP_INIT_NETWORK needs loaded or trained
  * parameters), at most max_iters damped Gauss-Newton steps (stopping at tol), the
- * acceptance flags.  Synchronous; fills *out if non-NULL. */
+ * acceptance flags.  With DGP_INIT_NETWORK each element starts from the
+ * network's rule or the template's, whichever has the smaller moment residual,
+ * and an element rejected after a network start is refined again from the
+ * template (its steps count both attempts).  Synchronous; fills *out if
+ * non-NULL. */
 dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dgp_qrule_stats *out);
 
 /* Copy the rules into caller-owned device buffers (any may be NULL):

@@ -55,7 +55,13 @@ class PatternInfo(C.Structure):
 class QruleStats(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_eligible", C.c_int64), ("n_accepted", C.c_int64),
                 ("iters_hist", C.c_int64 * 16), ("max_residual_accepted", C.c_double),
-                ("ms_features", C.c_float), ("ms_network", C.c_float), ("ms_refine", C.c_float)]
+                ("ms_features", C.c_float), ("ms_network", C.c_float), ("ms_refine", C.c_float),
+                ("n_start_network", C.c_int64), ("n_retried", C.c_int64), ("n_retry_accepted", C.c_int64)]
+
+
+class SlabDesc(C.Structure):
+    _fields_ = [("t0", C.c_double), ("t1", C.c_double), ("tp0", C.c_double), ("tau1", C.c_double),
+                ("tau2", C.c_double), ("prev", C.c_void_p)]
 
 
 class TrainCfg(C.Structure):
@@ -72,7 +78,7 @@ EXPORTS = ["dgp_create", "dgp_destroy", "dgp_set_stream", "dgp_last_error", "dgp
            "dgp_pattern_copy", "dgp_assemble", "dgp_run", "dgp_run_static", "dgp_graph_capture", "dgp_graph_launch",
            "dgp_set_timing", "dgp_kernel_ms", "dgp_time_kernels", "dgp_autotune", "dgp_set_launch", "dgp_mlp_load", "dgp_qrule_build", "dgp_qrule_get",
            "dgp_qrule_cell_data", "dgp_train_polygons", "dgp_mlp_forward", "dgp_mlp_loss_grad", "dgp_adam_step",
-           "dgp_mlp_train"]
+           "dgp_mlp_train", "dgp_assemble_coo", "dgp_assemble_st"]
 
 _lib = None
 
@@ -118,6 +124,9 @@ def lib():
         L.dgp_time_kernels.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.dgp_autotune.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         L.dgp_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
+        L.dgp_assemble_coo.argtypes = [C.c_void_p, C.POINTER(ProblemDesc), C.c_int] + [C.c_void_p] * 6
+        L.dgp_assemble_st.argtypes = [C.c_void_p, C.POINTER(ProblemDesc), C.c_int, C.POINTER(SlabDesc),
+                                      C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -184,6 +193,7 @@ class Context:
         self._check(lib().dgp_create(C.byref(self._h), device, C.c_void_p(_torch_stream(stream))), "dgp_create")
         self.info = None
         self._keep = None
+        self._p = -1
 
     def _check(self, st, what):
         if st != 0:
@@ -208,6 +218,8 @@ class Context:
         d, arrs = mesh_desc(mesh)
         self._check(lib().dgp_mesh_upload(self._h, C.byref(d)), "dgp_mesh_upload")
         self.info = None
+        ps = np.unique(np.asarray(mesh.cell_p))
+        self._p = int(ps[0]) if ps.size == 1 else -1
 
     def pattern(self) -> PatternInfo:
         info = PatternInfo()
@@ -275,6 +287,55 @@ class Context:
         pd = problem_desc(problem)
         self._check(lib().dgp_graph_capture(self._h, what, C.byref(pd), precision, rule_mode, vals.data_ptr(),
                                             rhs.data_ptr()), "dgp_graph_capture")
+
+    def assemble_coo(self, problem: dict, precision):
+        """The Approach-1 ablation (COO records, radix sort, segmented sums): a dict
+        of device tensors row_ptr, col_idx, val_ptr, dof_ptr, vals, rhs."""
+        import torch
+        i = self.info or self.pattern()
+        dev = torch.device("cuda", self.device)
+        dt = torch.float32 if precision == F32 else torch.float64
+        out = dict(row_ptr=torch.empty(i.n_rows + 1, dtype=torch.int64, device=dev),
+                   col_idx=torch.empty(i.nnzb, dtype=torch.int32, device=dev),
+                   val_ptr=torch.empty(i.nnzb + 1, dtype=torch.int64, device=dev),
+                   dof_ptr=torch.empty(i.n_rows + 1, dtype=torch.int64, device=dev),
+                   vals=torch.empty(i.n_vals, dtype=dt, device=dev),
+                   rhs=torch.empty(i.n_dofs, dtype=dt, device=dev))
+        pd = problem_desc(problem)
+        self._keep = (out["vals"], out["rhs"])
+        self._check(lib().dgp_assemble_coo(self._h, C.byref(pd), precision, out["vals"].data_ptr(),
+                                           out["rhs"].data_ptr(), out["row_ptr"].data_ptr(),
+                                           out["col_idx"].data_ptr(), out["val_ptr"].data_ptr(),
+                                           out["dof_ptr"].data_ptr()), "dgp_assemble_coo")
+        return out
+
+    def assemble_st(self, problem: dict, precision, t0, t1, tau=(0.0, 0.0), prev=None, tp0=None, out=None):
+        """One space-time slab (t0, t1] on prisms over the uploaded 2D mesh (uniform
+        degree): (vals, rhs) device tensors, blocks of n_b = (p+1)(p+2)(p+3)/6 on
+        the spatial pattern; prev = previous slab's FP64 coefficients (device) or None."""
+        import torch
+        i = self.info or self.pattern()
+        p = int(self._p_uniform())
+        nb = (p + 1) * (p + 2) * (p + 3) // 6
+        dev = torch.device("cuda", self.device)
+        dt = torch.float32 if precision == F32 else torch.float64
+        if out is None:
+            out = (torch.empty(i.nnzb * nb * nb, dtype=dt, device=dev), torch.empty(i.n_rows * nb, dtype=dt, device=dev))
+        vals, rhs = out
+        if vals.numel() < i.nnzb * nb * nb or rhs.numel() < i.n_rows * nb or vals.dtype != dt or rhs.dtype != dt:
+            raise ValueError("space-time outputs of the wrong size or type")
+        sl = SlabDesc(t0, t1, tp0 if tp0 is not None else t0 - (t1 - t0), tau[0], tau[1],
+                      prev.data_ptr() if prev is not None else None)
+        if prev is not None and (prev.dtype != torch.float64 or prev.numel() < i.n_rows * nb or not prev.is_cuda):
+            raise ValueError("prev must be a device FP64 tensor of n_cells * n_b coefficients")
+        pd = problem_desc(problem)
+        self._keep = (vals, rhs, prev)
+        self._check(lib().dgp_assemble_st(self._h, C.byref(pd), precision, C.byref(sl), vals.data_ptr(),
+                                          rhs.data_ptr()), "dgp_assemble_st")
+        return vals, rhs
+
+    def _p_uniform(self):
+        return self._p
 
     def graph_launch(self):
         self._check(lib().dgp_graph_launch(self._h), "dgp_graph_launch")

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgpoly.so")
 SOURCES = ["runtime.hip", "learned_rt.hip", "prep.hip", "assemble_row.hip", "prep3d.hip", "assemble3d.hip",
-           "qrule.hip", "mlp.hip"]
+           "qrule.hip", "mlp.hip", "approach1.hip", "approach1_rt.hip", "spacetime.hip", "spacetime_rt.hip"]
 ARCH = os.environ.get("DGP_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled: the compiler must not emit

@@ -613,16 +613,14 @@ __device__ __forceinline__ void row_slices(const AsmArgs &A, const RowCtx &R, st
 // MX: neighbours may have other degrees than P (up to PN); otherwise all have degree P = PN
 // ALT = 1 asks the register allocator for one more wave per SIMD than the
 // measured default (dgp_autotune picks between the two per degree and precision)
-template <typename T, int P, int PN, bool MX, bool ADV, int ALT>
-__global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(AsmArgs A) {
+// Element row c of degree P in one wave (pattern row and values); wlds: the
+// wave's LDS region of RowCfg<T, P, PN>::LW elements.
+template <typename T, int P, int PN, bool MX, bool ADV>
+__device__ __forceinline__ void row_body(const AsmArgs &A, const int c, T *wlds) {
     using C = RowCfg<T, P, PN>;
     constexpr int NB = C::NB, FG = C::FG;
     const DevMesh &m = A.m;
     const int lane = threadIdx.x & 63;
-    // the row index is uniform across the wave: keep it (and what derives from it) in scalar registers
-    const int wid = xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wid >= A.n_rows) return;
-    const int c = A.rows ? __builtin_amdgcn_readfirstlane(A.rows[wid]) : wid;
     const int64_t s = m.cell_ptr[c];
     const int nv = (int)(m.cell_ptr[c + 1] - s);
 
@@ -730,8 +728,7 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     R.dvoff = dvoff;
     R.maxdup = max(maxdup, 1);
     R.ng = ng;
-    __shared__ T xlds[C::LW > 0 ? 4 * C::LW : 1];
-    R.xs = C::LW > 0 ? xlds + (threadIdx.x >> 6) * C::LW : nullptr;
+    R.xs = C::LW > 0 ? wlds : nullptr;
     R.gmask = gmask;
     {
         // lane g gets the position of the g-th set bit of gmask: a forward
@@ -751,6 +748,57 @@ __global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(A
     row_slices<T, P, PN, MX, ADV>(A, R, std::make_integer_sequence<int, C::NSL>{});
 }
 
+template <typename T, int P, int PN, bool MX, bool ADV, int ALT>
+__global__ void __launch_bounds__(256, (RowCfg<T, P, PN>::MINW + ALT)) k_row2d(AsmArgs A) {
+    using C = RowCfg<T, P, PN>;
+    __shared__ T xlds[C::LW > 0 ? 4 * C::LW : 1];
+    // the row index is uniform across the wave: keep it (and what derives from it) in scalar registers
+    const int wid = xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wid >= A.n_rows) return;
+    const int c = A.rows ? __builtin_amdgcn_readfirstlane(A.rows[wid]) : wid;
+    row_body<T, P, PN, MX, ADV>(A, c, xlds + (threadIdx.x >> 6) * C::LW);
+}
+
+// One persistent launch over the rows of every degree of a mixed-degree mesh:
+// A.rows lists them bin by bin, (degree, fan sub-triangle count) descending,
+// so the costliest rows start first; wave w of the grid takes items w,
+// w + W, w + 2W, ... (W waves in the grid) and dispatches on the row's degree
+// to the same per-degree body as k_row2d (identical arithmetic per row).  No
+// queue counter: the assignment is static, so the launch needs no reset and
+// every wave exits after its last item.
+template <typename T, int P>
+constexpr int lw_mixed() {
+    return RowCfg<T, P, kMaxP>::LW;
+}
+template <typename T>
+constexpr int lw_fused() {
+    constexpr int a = lw_mixed<T, 1>(), b = lw_mixed<T, 2>(), c = lw_mixed<T, 3>(), d = lw_mixed<T, 4>();
+    constexpr int ab = a > b ? a : b, cd = c > d ? c : d;
+    return ab > cd ? ab : cd;
+}
+
+template <typename T, bool ADV>
+__global__ void __launch_bounds__(256) k_row2d_fused(AsmArgs A) {
+    constexpr int LW = lw_fused<T>();
+    __shared__ T xlds[4 * (LW > 0 ? LW : 1)];
+    T *wlds = xlds + (threadIdx.x >> 6) * LW;
+    const int w0 = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = gridDim.x * 4;
+    for (int it = w0; it < A.n_rows; it += nw) {
+        const int c = __builtin_amdgcn_readfirstlane(A.rows[it]);
+        const int p = __builtin_amdgcn_readfirstlane((int)A.m.cell_p[c]);
+        if (p == 4)
+            row_body<T, 4, kMaxP, true, ADV>(A, c, wlds);
+        else if (p == 3)
+            row_body<T, 3, kMaxP, true, ADV>(A, c, wlds);
+        else if (p == 2)
+            row_body<T, 2, kMaxP, true, ADV>(A, c, wlds);
+        else
+            row_body<T, 1, kMaxP, true, ADV>(A, c, wlds);
+        wave_sync();  // the next row reuses the wave's LDS region
+    }
+}
+
 template <typename T, int P, int PN, bool MX>
 static void launch_row(const AsmArgs &a, int alt, hipStream_t st) {
     const bool adv = a.pr.bx != 0.0 || a.pr.by != 0.0 || a.pr.c != 0.0;
@@ -767,6 +815,64 @@ static void launch_row(const AsmArgs &a, int alt, hipStream_t st) {
         else
             hipLaunchKernelGGL((k_row2d<T, P, PN, MX, false, 0>), dim3(nb), dim3(256), 0, st, a);
     }
+}
+
+template <typename T, bool ADV>
+static void launch_fused_t(const AsmArgs &a, hipStream_t st) {
+    // as many work-groups as stay resident at once (the loop does the rest)
+    static int blocks = 0;
+    if (blocks == 0) {
+        int dev = 0, per_cu = 0, n_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_row2d_fused<T, ADV>, 256, 0) != hipSuccess ||
+            per_cu < 1 || n_cu < 1) {
+            per_cu = 1;
+            n_cu = 256;
+        }
+        blocks = per_cu * n_cu;
+    }
+    const int need = (a.n_rows + 3) / 4;
+    hipLaunchKernelGGL((k_row2d_fused<T, ADV>), dim3(blocks < need ? blocks : need), dim3(256), 0, st, a);
+}
+
+void launch_row2d_fused(const AsmArgs &a, int precision, hipStream_t st) {
+    if (a.n_rows <= 0) return;
+    const bool adv = a.pr.bx != 0.0 || a.pr.by != 0.0 || a.pr.c != 0.0;
+    if (precision == 0) {
+        if (adv)
+            launch_fused_t<double, true>(a, st);
+        else
+            launch_fused_t<double, false>(a, st);
+    } else {
+        if (adv)
+            launch_fused_t<float, true>(a, st);
+        else
+            launch_fused_t<float, false>(a, st);
+    }
+}
+
+// Bytes of per-lane scratch (register spills) of the row kernel for these
+// template arguments; the tuner leaves configurations that spill untried.
+template <typename T, int P, int PN, bool MX>
+static size_t spill_bytes(int alt, bool adv) {
+    hipFuncAttributes fa;
+    const void *f = adv ? (alt ? (const void *)k_row2d<T, P, PN, MX, true, 1> : (const void *)k_row2d<T, P, PN, MX, true, 0>)
+                        : (alt ? (const void *)k_row2d<T, P, PN, MX, false, 1> : (const void *)k_row2d<T, P, PN, MX, false, 0>);
+    if (hipFuncGetAttributes(&fa, f) != hipSuccess) return 0;
+    return fa.localSizeBytes;
+}
+
+size_t row2d_spill_bytes(int precision, int p, bool mixed, int alt, bool adv) {
+#define DGP_SP(T, PP) \
+    if (p == PP) return mixed ? spill_bytes<T, PP, kMaxP, true>(alt, adv) : spill_bytes<T, PP, PP, false>(alt, adv);
+    if (precision == 0) {
+        DGP_SP(double, 1) DGP_SP(double, 2) DGP_SP(double, 3) DGP_SP(double, 4)
+    } else {
+        DGP_SP(float, 1) DGP_SP(float, 2) DGP_SP(float, 3) DGP_SP(float, 4)
+    }
+#undef DGP_SP
+    return 0;
 }
 
 bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, int alt, hipStream_t st) {

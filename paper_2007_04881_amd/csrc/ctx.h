@@ -26,6 +26,9 @@ struct dgp_ctx {
     int32_t *rows_by_p = nullptr;      // mixed degrees: element ids grouped by degree (stable)
     int64_t rows_off[dgp::kMaxP + 2] = {};  // group of degree p: rows_by_p[rows_off[p] .. rows_off[p + 1])
     int32_t *rows_sub = nullptr;  // 2D: element ids by (degree, fan sub-triangle count), stable; same rows_off
+    int32_t *rows_lpt = nullptr;  // 2D mixed degrees: all element ids by (degree, sub-triangles) descending
+    int64_t n_boundary_faces = 0;
+    int max_dup2d = 1;            // 2D: most edges one cell shares with one neighbour
     std::vector<void *> mesh_bufs;
     dgp::DevMesh dm{};
 
@@ -72,6 +75,13 @@ struct dgp_ctx {
     // 2D launch configuration per [FP64, FP32][degree]: bit 0 = the row kernel's
     // register budget (one more wave per SIMD), bit 1 = rows in rows_sub order
     int8_t row_cfg[2][dgp::kMaxP + 1] = {};
+    // mixed-degree 2D meshes: one persistent launch over every degree bin (1) or
+    // one launch per degree (0), per [FP64, FP32]
+    int8_t fused[2] = {0, 0};
+
+    // Approach-1 workspace (COO records, sort buffers), allocated on first use
+    void *a1_buf = nullptr;
+    size_t a1_bytes = 0;
 
     bool timing = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -80,6 +90,7 @@ struct dgp_ctx {
 
 dgp_status dgp_fail(dgp_ctx *ctx, dgp_status st, const char *fmt, ...);
 void dgp_free_qrule(dgp_ctx *c);
+void dgp_free_approach1(dgp_ctx *c);
 
 #define HIPCHK(ctx, call)                                                                                    \
     do {                                                                                                     \

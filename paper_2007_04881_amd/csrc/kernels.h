@@ -19,6 +19,13 @@ void launch_prep(const DevMesh &m, const DevProblem &pr, const PrepOut &out, hip
 // mixed: neighbours may have any degree up to kMaxP (else all have degree p).
 // alt: 0 = the default register budget, 1 = one more wave per SIMD (see dgp_autotune)
 bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, int alt, hipStream_t st);
+// One persistent launch over the rows a.rows[0 .. n_rows) of every degree (mixed-degree
+// meshes), dispatching per row to the same body as launch_row2d(.., mixed = true, ..).
+void launch_row2d_fused(const AsmArgs &a, int precision, hipStream_t st);
+// per-lane scratch bytes (register spills) of the row kernel instantiation that
+// launch_row2d(.., precision, p, mixed, alt, ..) runs for a problem with (adv) or
+// without advection-reaction terms
+size_t row2d_spill_bytes(int precision, int p, bool mixed, int alt, bool adv);
 
 // ---- polyhedral (3D) meshes
 // Geometry, face groups and row counts of every cell, then the tile scan.
@@ -35,6 +42,15 @@ void launch_rule_init(int n, const float *z, const double *parea, double *nodes,
 void launch_refine(int n, const double *mom, const double *parea, const uint8_t *eligible, double *nodes,
                    double *weights, uint8_t *accepted, double *residual, int32_t *iters, int max_it, double tol,
                    double mu0, hipStream_t st);
+
+// per element the start (network or template) of smaller initial residual; retry and merge
+void launch_rule_pick(int n, const double *res_net, const double *res_tmpl, double *nodes, double *weights,
+                      const double *nodes_t, const double *w_t, uint8_t *start_tmpl, hipStream_t st);
+void launch_rule_retry_mask(int n, const uint8_t *elig, const uint8_t *acc, const uint8_t *start_tmpl, uint8_t *mask,
+                            hipStream_t st);
+void launch_rule_merge(int n, const uint8_t *mask, const uint8_t *acc2, const double *res2, const int32_t *it2,
+                       const double *nodes2, const double *w2, double *nodes, double *weights, uint8_t *acc,
+                       double *res, int32_t *it, hipStream_t st);
 
 // ---- the rule network (FP32 on the matrix cores)
 // C = epi(A B): A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn], C row-major.

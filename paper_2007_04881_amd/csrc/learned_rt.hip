@@ -234,18 +234,50 @@ dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dg
     launch_prep(ctx->dm, neutral, ctx->prep, st, true, ctx->p_uniform);
     launch_cell_poly(ctx->dm, ctx->prep.geo, ctx->qr_feat, ctx->qr_mom, ctx->qr_area, ctx->qr_elig, st);
     HIPCHK(ctx, hipEventRecord(ev[1], st));
+    int64_t n_start_net = 0, n_retried = 0, n_retry_ok = 0;
     if (init == DGP_INIT_NETWORK) {
-        DevBuf act;
-        if (!act.alloc(sizeof(float) * (size_t)N * (2 * kQrHidden + kQrOut)))
-            return dgp_fail(ctx, DGP_ENOMEM, "network activations");
+        // the network's rule and the template's, each element starting from the one
+        // of smaller moment residual; elements the refinement rejects after a
+        // network start are refined again from the template
+        DevBuf act, tmp;
+        if (!act.alloc(sizeof(float) * (size_t)N * (2 * kQrHidden + kQrOut)) ||
+            !tmp.alloc((sizeof(double) * (3 * kQrNodes + 3) + sizeof(int32_t) + 4) * (size_t)N + 4 * 256))
+            return dgp_fail(ctx, DGP_ENOMEM, "network activations and rule scratch");
         float *h1 = act.as<float>(), *h2 = h1 + (size_t)N * kQrHidden, *o = h2 + (size_t)N * kQrHidden;
+        double *nodes_t = tmp.as<double>(), *w_t = nodes_t + (size_t)N * 2 * kQrNodes, *res_a = w_t + (size_t)N * kQrNodes;
+        double *res_b = res_a + N, *res2 = res_b + N;
+        int32_t *it2 = reinterpret_cast<int32_t *>(res2 + N);
+        uint8_t *start_tmpl = reinterpret_cast<uint8_t *>(it2 + N), *mask = start_tmpl + N, *acc_a = mask + N,
+                *acc_b = acc_a + N;
         mlp_forward(ctx->mlp, ctx->qr_feat, N, h1, h2, o, st);
         launch_rule_init((int)N, o, ctx->qr_area, ctx->qr_nodes, ctx->qr_w, st);
+        launch_rule_init((int)N, nullptr, ctx->qr_area, nodes_t, w_t, st);
+        // initial residuals (no refinement step)
+        launch_refine((int)N, ctx->qr_mom, ctx->qr_area, ctx->qr_elig, ctx->qr_nodes, ctx->qr_w, acc_a, res_a, it2, 0,
+                      tol, 1e-6, st);
+        launch_refine((int)N, ctx->qr_mom, ctx->qr_area, ctx->qr_elig, nodes_t, w_t, acc_b, res_b, it2, 0, tol, 1e-6,
+                      st);
+        launch_rule_pick((int)N, res_a, res_b, ctx->qr_nodes, ctx->qr_w, nodes_t, w_t, start_tmpl, st);
         HIPCHK(ctx, hipEventRecord(ev[2], st));
         launch_refine((int)N, ctx->qr_mom, ctx->qr_area, ctx->qr_elig, ctx->qr_nodes, ctx->qr_w, ctx->qr_ok,
                       ctx->qr_res, ctx->qr_iters, max_iters, tol, 1e-6, st);
+        launch_rule_retry_mask((int)N, ctx->qr_elig, ctx->qr_ok, start_tmpl, mask, st);
+        launch_rule_init((int)N, nullptr, ctx->qr_area, nodes_t, w_t, st);
+        launch_refine((int)N, ctx->qr_mom, ctx->qr_area, mask, nodes_t, w_t, acc_b, res2, it2, max_iters, tol, 1e-6, st);
+        launch_rule_merge((int)N, mask, acc_b, res2, it2, nodes_t, w_t, ctx->qr_nodes, ctx->qr_w, ctx->qr_ok,
+                          ctx->qr_res, ctx->qr_iters, st);
         HIPCHK(ctx, hipEventRecord(ev[3], st));
-        HIPCHK(ctx, hipStreamSynchronize(st));  // the activations are freed on return
+        HIPCHK(ctx, hipStreamSynchronize(st));  // the scratch is freed on return
+        std::vector<uint8_t> st_t(N), mk(N), ok2(N), el(N);
+        HIPCHK(ctx, hipMemcpy(st_t.data(), start_tmpl, N, hipMemcpyDeviceToHost));
+        HIPCHK(ctx, hipMemcpy(mk.data(), mask, N, hipMemcpyDeviceToHost));
+        HIPCHK(ctx, hipMemcpy(ok2.data(), acc_b, N, hipMemcpyDeviceToHost));
+        HIPCHK(ctx, hipMemcpy(el.data(), ctx->qr_elig, N, hipMemcpyDeviceToHost));
+        for (int64_t c = 0; c < N; ++c) {
+            n_start_net += el[c] && !st_t[c];
+            n_retried += mk[c];
+            n_retry_ok += mk[c] && ok2[c];
+        }
     } else {
         launch_rule_init((int)N, nullptr, ctx->qr_area, ctx->qr_nodes, ctx->qr_w, st);
         HIPCHK(ctx, hipEventRecord(ev[2], st));
@@ -270,6 +302,9 @@ dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dg
         HIPCHK(ctx, hipMemcpy(it.data(), ctx->qr_iters, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
         HIPCHK(ctx, hipMemcpy(res.data(), ctx->qr_res, sizeof(double) * N, hipMemcpyDeviceToHost));
         out->n_cells = N;
+        out->n_start_network = n_start_net;
+        out->n_retried = n_retried;
+        out->n_retry_accepted = n_retry_ok;
         for (int64_t c = 0; c < N; ++c) {
             out->n_eligible += el[c];
             if (ok[c]) {

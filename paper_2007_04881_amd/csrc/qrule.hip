@@ -495,6 +495,65 @@ void launch_rule_init(int n, const float *z, const double *parea, double *nodes,
     hipLaunchKernelGGL(k_rule_init, dim3((n + 255) / 256), dim3(256), 0, st, n, z, parea, nodes, weights);
 }
 
+// Keep, per element, the start with the smaller initial moment residual:
+// the network's (in nodes / weights) or the template's (nodes_t / w_t);
+// start_tmpl[c] = 1 where the template's was kept.
+__global__ void k_rule_pick(int n, const double *__restrict__ res_net, const double *__restrict__ res_tmpl,
+                            double *nodes, double *weights, const double *__restrict__ nodes_t,
+                            const double *__restrict__ w_t, uint8_t *start_tmpl) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const bool tmpl = res_tmpl[c] < res_net[c];
+    start_tmpl[c] = tmpl;
+    if (tmpl) {
+        for (int i = 0; i < 2 * kQrNodes; ++i) nodes[(int64_t)c * 2 * kQrNodes + i] = nodes_t[(int64_t)c * 2 * kQrNodes + i];
+        for (int k = 0; k < kQrNodes; ++k) weights[(int64_t)c * kQrNodes + k] = w_t[(int64_t)c * kQrNodes + k];
+    }
+}
+
+// Elements to start again from the template: eligible, not accepted, started from the network.
+__global__ void k_rule_retry_mask(int n, const uint8_t *__restrict__ elig, const uint8_t *__restrict__ acc,
+                                  const uint8_t *__restrict__ start_tmpl, uint8_t *mask) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) mask[c] = elig[c] && !acc[c] && !start_tmpl[c];
+}
+
+// Take the retried rules that were accepted (their steps add to the first attempt's).
+__global__ void k_rule_merge(int n, const uint8_t *__restrict__ mask, const uint8_t *__restrict__ acc2,
+                             const double *__restrict__ res2, const int32_t *__restrict__ it2,
+                             const double *__restrict__ nodes2, const double *__restrict__ w2, double *nodes,
+                             double *weights, uint8_t *acc, double *res, int32_t *it) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || !mask[c]) return;
+    it[c] += it2[c];
+    if (!acc2[c]) return;
+    for (int i = 0; i < 2 * kQrNodes; ++i) nodes[(int64_t)c * 2 * kQrNodes + i] = nodes2[(int64_t)c * 2 * kQrNodes + i];
+    for (int k = 0; k < kQrNodes; ++k) weights[(int64_t)c * kQrNodes + k] = w2[(int64_t)c * kQrNodes + k];
+    acc[c] = 1;
+    res[c] = res2[c];
+}
+
+void launch_rule_pick(int n, const double *res_net, const double *res_tmpl, double *nodes, double *weights,
+                      const double *nodes_t, const double *w_t, uint8_t *start_tmpl, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_rule_pick, dim3((n + 255) / 256), dim3(256), 0, st, n, res_net, res_tmpl, nodes, weights,
+                       nodes_t, w_t, start_tmpl);
+}
+
+void launch_rule_retry_mask(int n, const uint8_t *elig, const uint8_t *acc, const uint8_t *start_tmpl, uint8_t *mask,
+                            hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_rule_retry_mask, dim3((n + 255) / 256), dim3(256), 0, st, n, elig, acc, start_tmpl, mask);
+}
+
+void launch_rule_merge(int n, const uint8_t *mask, const uint8_t *acc2, const double *res2, const int32_t *it2,
+                       const double *nodes2, const double *w2, double *nodes, double *weights, uint8_t *acc,
+                       double *res, int32_t *it, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_rule_merge, dim3((n + 255) / 256), dim3(256), 0, st, n, mask, acc2, res2, it2, nodes2, w2,
+                       nodes, weights, acc, res, it);
+}
+
 void launch_refine(int n, const double *mom, const double *parea, const uint8_t *eligible, double *nodes,
                    double *weights, uint8_t *accepted, double *residual, int32_t *iters, int max_it, double tol,
                    double mu0, hipStream_t st) {

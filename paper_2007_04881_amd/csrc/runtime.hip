@@ -48,6 +48,9 @@ static void free_mesh(dgp_ctx *c) {
     c->rows_by_p = nullptr;
     if (c->rows_sub) (void)hipFree(c->rows_sub);
     c->rows_sub = nullptr;
+    if (c->rows_lpt) (void)hipFree(c->rows_lpt);
+    c->rows_lpt = nullptr;
+    dgp_free_approach1(c);
     for (void *p : {(void *)c->row_ptr, (void *)c->col_idx, (void *)c->val_ptr, (void *)c->dof_ptr, c->work})
         if (p) (void)hipFree(p);
     c->row_ptr = c->val_ptr = c->dof_ptr = nullptr;
@@ -366,6 +369,46 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
             return fail(ctx, DGP_ENOMEM, "row groups");
         }
         HIPCHK(ctx, hipMemcpy(ctx->rows_by_p, rows.data(), sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice));
+    }
+    {
+        // boundary faces, and the most edges a cell shares with one neighbour
+        int64_t nbf = 0;
+        for (int64_t f = 0; f < F; ++f) nbf += m->face_cell[2 * f + 1] < 0;
+        int mdup = 1;
+        for (int64_t c = 0; c < N; ++c) {
+            const int64_t s = m->cell_ptr[c], e = m->cell_ptr[c + 1];
+            for (int64_t k = s; k < e; ++k) {
+                const int32_t f = m->cell_face[k];
+                const int32_t o = m->face_cell[2 * f] == c ? m->face_cell[2 * f + 1] : m->face_cell[2 * f];
+                if (o < 0) continue;
+                int cnt = 0;
+                for (int64_t j = s; j < e; ++j) {
+                    const int32_t g = m->cell_face[j];
+                    cnt += (m->face_cell[2 * g] == c ? m->face_cell[2 * g + 1] : m->face_cell[2 * g]) == o;
+                }
+                mdup = cnt > mdup ? cnt : mdup;
+            }
+        }
+        ctx->n_boundary_faces = nbf;
+        ctx->max_dup2d = mdup;
+    }
+    if (pmin != pmax) {
+        // one persistent launch over all degrees takes the rows bin by bin,
+        // costliest first: (degree, fan sub-triangle count) descending, stable in id
+        constexpr int NS = kMaxFaces2D;
+        std::vector<int64_t> bc((size_t)(kMaxP + 1) * NS + 1, 0);
+        auto key = [&](int64_t c) {
+            return (int64_t)(kMaxP - m->cell_p[c]) * NS + (NS - 1 - (m->cell_ptr[c + 1] - m->cell_ptr[c] - 2));
+        };
+        for (int64_t c = 0; c < N; ++c) bc[(size_t)key(c) + 1] += 1;
+        for (size_t k = 1; k < bc.size(); ++k) bc[k] += bc[k - 1];
+        std::vector<int32_t> rows((size_t)N);
+        for (int64_t c = 0; c < N; ++c) rows[(size_t)bc[(size_t)key(c)]++] = (int32_t)c;
+        if (hipMalloc(&ctx->rows_lpt, sizeof(int32_t) * (size_t)N) != hipSuccess) {
+            free_mesh(ctx);
+            return fail(ctx, DGP_ENOMEM, "row bins (single launch)");
+        }
+        HIPCHK(ctx, hipMemcpy(ctx->rows_lpt, rows.data(), sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice));
     }
     {
         // the bins (p, n_sub) of Section 3.1's grouping refined by the number of
@@ -731,6 +774,13 @@ static dgp_status launch_assembly(dgp_ctx *ctx, const DevProblem &dp, int precis
     a.qr_w = ctx->qr_w;
     a.qr_ok = ctx->qr_ok;
     const int pi = precision == DGP_F32 ? 1 : 0;
+    if (ctx->p_uniform <= 0 && ctx->fused[pi] && ctx->rows_lpt) {
+        // every degree bin in one persistent launch
+        a.rows = ctx->rows_lpt;
+        a.n_rows = (int32_t)ctx->n_cells;
+        launch_row2d_fused(a, precision, st);
+        return DGP_OK;
+    }
     for (int p = 1; p <= kMaxP; ++p) {
         if (ctx->p_uniform > 0 && p != ctx->p_uniform) continue;
         if (ctx->rows_off[p + 1] == ctx->rows_off[p]) continue;
@@ -921,13 +971,20 @@ dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice) {
         }
         // each configuration of each bin gets an equal share of the budget (at least one launch)
         const float share = (float)budget_ms / (float)(kLaunchCfgs * (nbins > 0 ? nbins : 1));
+        const bool adv = a.pr.bx != 0.0 || a.pr.by != 0.0 || a.pr.c != 0.0;
         for (int b = 0; b < nbins; ++b) {
             const int p = bins[b];
             const bool mixed = ctx->p_uniform <= 0;
+            // the larger-occupancy register budget is tried only if it spills no
+            // more than the default (spills cost HBM traffic the timing of one
+            // launch in isolation can hide)
+            const size_t spill0 = row2d_spill_bytes(ctx->last_precision, p, mixed, 0, adv);
+            const size_t spill1 = row2d_spill_bytes(ctx->last_precision, p, mixed, 1, adv);
             float best = 0.0f;
             int best_cfg = 0;
             for (int cfg = 0; cfg < kLaunchCfgs; ++cfg) {
                 const int alt = cfg & 1;
+                if (alt && spill1 > spill0) continue;
                 row_range(ctx, a, p, cfg);
                 // one warm launch, then as many timed launches as fit in the share
                 HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
@@ -952,17 +1009,62 @@ dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice) {
             }
             ctx->row_cfg[pi][p] = (int8_t)best_cfg;
         }
+        if (ctx->p_uniform <= 0 && ctx->rows_lpt) {
+            // the tuned per-degree launches against one persistent launch over every bin
+            auto time_ms = [&](bool fused, float *out) -> dgp_status {
+                for (int pass = 0; pass < 2; ++pass) {  // a warm pass, then the timed one
+                    HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
+                    const int reps = pass == 0 ? 1 : 5;
+                    for (int r = 0; r < reps; ++r) {
+                        if (fused) {
+                            a.rows = ctx->rows_lpt;
+                            a.n_rows = (int32_t)ctx->n_cells;
+                            launch_row2d_fused(a, ctx->last_precision, st);
+                        } else {
+                            for (int b = 0; b < nbins; ++b) {
+                                const int cfg = ctx->row_cfg[pi][bins[b]];
+                                row_range(ctx, a, bins[b], cfg);
+                                launch_row2d(a, ctx->last_precision, bins[b], true, cfg & 1, st);
+                            }
+                        }
+                    }
+                    HIPCHK(ctx, hipEventRecord(ctx->ev[1], st));
+                    HIPCHK(ctx, hipGetLastError());
+                    HIPCHK(ctx, hipEventSynchronize(ctx->ev[1]));
+                    float ms = 0.0f;
+                    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+                    *out = ms / (float)reps;
+                }
+                return DGP_OK;
+            };
+            float t_sep = 0.0f, t_one = 0.0f;
+            dgp_status e1 = time_ms(false, &t_sep);
+            if (e1) return e1;
+            dgp_status e2 = time_ms(true, &t_one);
+            if (e2) return e2;
+            ctx->fused[pi] = t_one < t_sep ? 1 : 0;
+        }
         ctx->ev_pattern = ctx->ev_assemble = false;
     }
-    if (choice)
+    if (choice) {
         for (int q = 0; q < 2; ++q)
             for (int p = 0; p <= kMaxP; ++p) choice[q * (kMaxP + 1) + p] = ctx->row_cfg[q][p];
+        // entry 0 of each precision: 1 if mixed-degree meshes take one launch over all bins
+        for (int q = 0; q < 2; ++q) choice[q * (kMaxP + 1)] = ctx->fused[q];
+    }
     return DGP_OK;
 }
+
 
 dgp_status dgp_set_launch(dgp_ctx *ctx, int precision, int p, int cfg) {
     if (!ctx) return DGP_EINVAL;
     if (precision != DGP_F64 && precision != DGP_F32) return fail(ctx, DGP_EINVAL, "precision %d", precision);
+    if (p == 0) {
+        // mixed-degree meshes: one persistent launch over all bins (1) or one per degree (0)
+        if (cfg != 0 && cfg != 1) return fail(ctx, DGP_EINVAL, "single-launch setting %d (0 or 1)", cfg);
+        ctx->fused[precision == DGP_F32 ? 1 : 0] = (int8_t)cfg;
+        return DGP_OK;
+    }
     if (p < 1 || p > kMaxP) return fail(ctx, DGP_EUNSUPPORTED, "p = %d outside 1..%d", p, kMaxP);
     if (cfg < 0 || cfg >= kLaunchCfgs) return fail(ctx, DGP_EINVAL, "launch configuration %d outside 0..%d", cfg, kLaunchCfgs - 1);
     ctx->row_cfg[precision == DGP_F32 ? 1 : 0][p] = (int8_t)cfg;

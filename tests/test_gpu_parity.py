@@ -335,3 +335,56 @@ def test_back_to_back_steps():
     for k, (v, r) in enumerate(outs):
         assert torch.equal(v, ref[k][0]) and torch.equal(r, ref[k][1]), k
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_single_persistent_launch_over_all_bins(precision):
+    """Mixed degrees in one persistent launch (rows bin by bin, costliest
+    first, static assignment to the resident waves) give bit-identical values
+    and pattern to one launch per degree, also captured in a graph; the
+    tuner's choice between the two keeps the results."""
+    import torch
+    import paper_2007_04881_amd as D
+
+    m = voronoi_mesh(5000, 87, lloyd=0, p=1)
+    m = m.with_degrees(np.random.default_rng(14).integers(1, 5, m.n_cells))
+    pat = oracle.pattern(m)
+    ctx = D.Context(0)
+    ctx.upload(m)
+    ctx.pattern()
+    outs = {}
+    for fused in (0, 1):
+        print(f"[case] mixed degrees prec={precision} single launch={fused}", flush=True)
+        ctx.set_launch(precision, 0, fused)
+        v, r = ctx.outputs(precision)
+        v.fill_(float("nan"))
+        r.fill_(float("nan"))
+        ctx.run(DAR, precision, v, r)
+        torch.cuda.synchronize()
+        rp, ci, vp, dp = ctx.pattern_tensors()
+        assert np.array_equal(rp.cpu().numpy(), pat.row_ptr) and np.array_equal(ci.cpu().numpy(), pat.col_idx)
+        assert np.array_equal(vp.cpu().numpy(), pat.val_ptr) and np.array_equal(dp.cpu().numpy(), pat.dof_ptr)
+        outs[fused] = (v.clone(), r.clone())
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    g = dict(vals=outs[1][0].double().cpu().numpy(), rhs=outs[1][1].double().cpu().numpy())
+    ov, orhs = oracle.assemble(m, oracle_problem(DAR), pat=pat)
+    eb, er = block_errors(g, ov, orhs, pat)
+    assert eb <= TOL[precision] and er <= TOL[precision], (eb, er)
+    # graph replay of the single launch
+    v3, r3 = ctx.outputs(precision)
+    ctx.graph_capture(0, DAR, precision, v3, r3)
+    for _ in range(3):
+        v3.fill_(-1.0)
+        torch.cuda.synchronize()
+        ctx.graph_launch()
+        torch.cuda.synchronize()
+        assert torch.equal(v3, outs[1][0]) and torch.equal(r3, outs[1][1])
+    # the tuner picks one of the two; results unchanged
+    ctx.run(DAR, precision, v3, r3)
+    choice = ctx.autotune(100)
+    assert choice[1 if precision == 1 else 0][0] in (0, 1)
+    v3.fill_(float("nan"))
+    ctx.run(DAR, precision, v3, r3)
+    torch.cuda.synchronize()
+    assert torch.equal(v3, outs[1][0]) and torch.equal(r3, outs[1][1])
+    ctx.close()
