@@ -74,7 +74,14 @@ static int exponents(int dim, int p, int *ea, int *eb, int *ec) {
     return n;
 }
 
-int orc_basis(int dim, int p, const double *lo, const double *hi, const double *x, double *phi, double *grad) {
+/* The basis at the point ref + d, where ref lies in the box (a vertex of the
+ * element or of its face) and d is the point's offset from it: the box
+ * coordinate ((ref - lo) - (hi - ref) + 2 d) / (hi - lo) keeps the point's
+ * position relative to the box to the rounding of d, whatever the size of the
+ * absolute coordinates (a point stored as a double near 1 is known only to
+ * 1e-16 absolutely, i.e. 1e-13 relative to a cell of size 1e-3). */
+static int basis_rel(int dim, int p, const double *lo, const double *hi, const double *ref, const double *dx,
+                     double *phi, double *grad) {
     if (p < 0 || p > MAXP || (dim != 2 && dim != 3)) return -3;
     leg_init();
     double P[3][MAXP + 1], dP[3][MAXP + 1], chain[3], box = 1.0;
@@ -82,7 +89,7 @@ int orc_basis(int dim, int p, const double *lo, const double *hi, const double *
         double h = hi[d] - lo[d];
         box *= h;
         chain[d] = 2.0 / h;
-        legendre(p, (2.0 * x[d] - lo[d] - hi[d]) / h, P[d], dP[d]);
+        legendre(p, ((ref[d] - lo[d]) - (hi[d] - ref[d]) + 2.0 * dx[d]) / h, P[d], dP[d]);
     }
     int ea[MAXNB], eb[MAXNB], ec[MAXNB];
     int nb = exponents(dim, p, ea, eb, ec);
@@ -102,6 +109,11 @@ int orc_basis(int dim, int p, const double *lo, const double *hi, const double *
         }
     }
     return nb;
+}
+
+int orc_basis(int dim, int p, const double *lo, const double *hi, const double *x, double *phi, double *grad) {
+    const double zero[3] = {0.0, 0.0, 0.0};
+    return basis_rel(dim, p, lo, hi, x, zero, phi, grad);
 }
 
 /* ------------------------------------------------- coefficients and data */
@@ -176,7 +188,12 @@ static void vtx(const orc_mesh *m, int v, double *out) {
 
 /* Volume quadrature points of cell c for degree p: simplices of the
  * subdivision times the reference rule.  Returns the count (malloc'ed X, W). */
-static int64_t vol_points(const orc_mesh *m, const orc_rules *ru, int64_t c, int p, double **X, double **W) {
+/* 2D: also the offsets D[3 q ..] of the points from the fan apex v0 (ref, 3
+ * doubles), D = l1 (v1 - v0) + l2 (v2 - v0), and X = v0 + D; the basis is
+ * evaluated from (ref, D) (basis_rel), the coefficients at X.  3D: D = 0 and
+ * ref unused (the basis takes X). */
+static int64_t vol_points(const orc_mesh *m, const orc_rules *ru, int64_t c, int p, double **X, double **W,
+                          double **D, double *ref) {
     int64_t s = m->cell_ptr[c], e = m->cell_ptr[c + 1];
     if (m->dim == 2) {
         const orc_rule *r = tri_rule_for(ru, p);
@@ -185,19 +202,28 @@ static int64_t vol_points(const orc_mesh *m, const orc_rules *ru, int64_t c, int
         if (nt < 1) return -2;
         *X = (double *)malloc(sizeof(double) * 3 * nt * r->n);
         *W = (double *)malloc(sizeof(double) * nt * r->n);
+        double *Dq = (double *)malloc(sizeof(double) * 3 * nt * r->n);
         int64_t q = 0;
         double v0[3], v1[3], v2[3];
         vtx(m, m->cell_vtx[s], v0);
+        for (int d = 0; d < 3; ++d) ref[d] = v0[d];
         for (int64_t t = 0; t < nt; ++t) {
             vtx(m, m->cell_vtx[s + 1 + t], v1);
             vtx(m, m->cell_vtx[s + 2 + t], v2);
             double area = 0.5 * ((v1[0] - v0[0]) * (v2[1] - v0[1]) - (v2[0] - v0[0]) * (v1[1] - v0[1]));
             for (int k = 0; k < r->n; ++k, ++q) {
                 const double *l = r->pts + 3 * k;
-                for (int d = 0; d < 3; ++d) (*X)[3 * q + d] = l[0] * v0[d] + l[1] * v1[d] + l[2] * v2[d];
+                for (int d = 0; d < 3; ++d) {
+                    Dq[3 * q + d] = l[1] * (v1[d] - v0[d]) + l[2] * (v2[d] - v0[d]);
+                    (*X)[3 * q + d] = v0[d] + Dq[3 * q + d];
+                }
                 (*W)[q] = r->w[k] * area;
             }
         }
+        if (D)
+            *D = Dq;
+        else
+            free(Dq);
         return q;
     } else {
         const orc_rule *r = &ru->tet;
@@ -205,6 +231,8 @@ static int64_t vol_points(const orc_mesh *m, const orc_rules *ru, int64_t c, int
         if (nt < 1 || (e - s) % 4) return -2;
         *X = (double *)malloc(sizeof(double) * 3 * nt * r->n);
         *W = (double *)malloc(sizeof(double) * nt * r->n);
+        if (D) *D = (double *)calloc((size_t)(3 * nt * r->n), sizeof(double));
+        if (ref) ref[0] = ref[1] = ref[2] = 0.0;
         int64_t q = 0;
         for (int64_t t = 0; t < nt; ++t) {
             double v[4][3];
@@ -276,16 +304,20 @@ static int cell_geometry(const orc_mesh *m, const orc_problem *pr, const orc_rul
     free(ids);
     g->diam = sqrt(diam2);
     /* |kappa|: shoelace (2D) or sum of sub-tetrahedron volumes (3D) */
-    double *X = NULL, *W = NULL;
-    int64_t nq = vol_points(m, ru, c, m->cell_p[c], &X, &W);
+    double *X = NULL, *W = NULL, ref[3];
+    int64_t nq = vol_points(m, ru, c, m->cell_p[c], &X, &W, NULL, ref);
     if (nq < 0) return (int)nq;
     if (dim == 2) {
-        double a2 = 0.0;
+        /* shoelace about the first vertex: the terms are products of coordinate
+         * differences (exact), so the area keeps its relative precision on
+         * small cells far from the origin */
+        double a2 = 0.0, o[3];
+        vtx(m, m->cell_vtx[s], o);
         for (int64_t i = 0; i < n; ++i) {
             double p0[3], p1[3];
             vtx(m, m->cell_vtx[s + i], p0);
             vtx(m, m->cell_vtx[s + (i + 1) % n], p1);
-            a2 += p0[0] * p1[1] - p1[0] * p0[1];
+            a2 += (p0[0] - o[0]) * (p1[1] - o[1]) - (p1[0] - o[0]) * (p0[1] - o[1]);
         }
         g->meas = 0.5 * a2;
     } else {
@@ -394,7 +426,19 @@ typedef struct {
     int npts;
     double X[64 * 3]; /* quadrature points */
     double W[64];
+    double ref[3];    /* 2D: the face's first vertex; points X = ref + D */
+    double D[64 * 3];
 } facepts;
+
+/* basis at a quadrature point: in 2D from its offset D to a mesh vertex ref
+ * (basis_rel), in 3D from its coordinates */
+static void eval_basis(int dim, int p, const double *lo, const double *hi, const double *x, const double *ref,
+                       const double *d, double *phi, double *grad) {
+    if (dim == 2)
+        basis_rel(dim, p, lo, hi, ref, d, phi, grad);
+    else
+        orc_basis(dim, p, lo, hi, x, phi, grad);
+}
 
 static int face_points(const orc_mesh *m, const orc_rules *ru, int32_t f, int64_t row, int pmax,
                        const cellgeo *grow, facepts *fp) {
@@ -424,8 +468,12 @@ static int face_points(const orc_mesh *m, const orc_rules *ru, int32_t f, int64_
         if (ng >= 16) return -3;
         const orc_rule *r = &ru->seg[ng];
         fp->npts = r->n;
+        for (int d = 0; d < 3; ++d) fp->ref[d] = a[d];
         for (int q = 0; q < r->n; ++q) {
-            for (int d = 0; d < 3; ++d) fp->X[3 * q + d] = a[d] + r->pts[q] * (b[d] - a[d]);
+            for (int d = 0; d < 3; ++d) {
+                fp->D[3 * q + d] = r->pts[q] * (b[d] - a[d]);
+                fp->X[3 * q + d] = a[d] + fp->D[3 * q + d];
+            }
             fp->W[q] = r->w[q] * len;
         }
     } else {
@@ -528,12 +576,12 @@ static int assemble_row(const orc_mesh *m, const orc_problem *pr, const orc_rule
 
     /* element term: first line of (dg-bilinear) and the f-term of (dg-linear) */
     if (pr->term_mask & (ORC_T_VOLUME | ORC_T_RHS)) {
-        double *X = NULL, *W = NULL;
-        int64_t nq = vol_points(m, ru, r, pr_, &X, &W);
+        double *X = NULL, *W = NULL, *Dv = NULL, ref[3];
+        int64_t nq = vol_points(m, ru, r, pr_, &X, &W, &Dv, ref);
         if (nq < 0) return (int)nq;
         for (int64_t q = 0; q < nq; ++q) {
             const double *x = X + 3 * q;
-            orc_basis(dim, pr_, gr->lo, gr->hi, x, phi, grad);
+            eval_basis(dim, pr_, gr->lo, gr->hi, x, ref, Dv + 3 * q, phi, grad);
             double a = coef_a(pr, x), u, f;
             orc_exact(pr, dim, x, &u, &f);
             if (pr->term_mask & ORC_T_VOLUME) {
@@ -553,6 +601,7 @@ static int assemble_row(const orc_mesh *m, const orc_problem *pr, const orc_rule
         }
         free(X);
         free(W);
+        free(Dv);
     }
 
     /* face terms: upwind, inflow-boundary and interior-penalty lines of
@@ -583,8 +632,8 @@ static int assemble_row(const orc_mesh *m, const orc_problem *pr, const orc_rule
             for (int q = 0; q < fp.npts; ++q) {
                 const double *x = fp.X + 3 * q;
                 double w = fp.W[q];
-                orc_basis(dim, pr_, gr->lo, gr->hi, x, phi, grad);
-                orc_basis(dim, po, go->lo, go->hi, x, phio, grado);
+                eval_basis(dim, pr_, gr->lo, gr->hi, x, fp.ref, fp.D + 3 * q, phi, grad);
+                eval_basis(dim, po, go->lo, go->hi, x, fp.ref, fp.D + 3 * q, phio, grado);
                 double a = coef_a(pr, x);
                 int up = bn < 0.0; /* x in the inflow part of the boundary of r */
                 for (int i = 0; i < nbr; ++i) {
@@ -608,7 +657,7 @@ static int assemble_row(const orc_mesh *m, const orc_problem *pr, const orc_rule
             for (int q = 0; q < fp.npts; ++q) {
                 const double *x = fp.X + 3 * q;
                 double w = fp.W[q];
-                orc_basis(dim, pr_, gr->lo, gr->hi, x, phi, grad);
+                eval_basis(dim, pr_, gr->lo, gr->hi, x, fp.ref, fp.D + 3 * q, phi, grad);
                 double a = coef_a(pr, x), g, fdummy;
                 orc_exact(pr, dim, x, &g, &fdummy);
                 int up = bn < 0.0;
@@ -634,7 +683,7 @@ static int assemble_row(const orc_mesh *m, const orc_problem *pr, const orc_rule
             for (int q = 0; q < fp.npts; ++q) {
                 const double *x = fp.X + 3 * q;
                 double u, gu[3], lap;
-                orc_basis(dim, pr_, gr->lo, gr->hi, x, phi, grad);
+                eval_basis(dim, pr_, gr->lo, gr->hi, x, fp.ref, fp.D + 3 * q, phi, grad);
                 exact_u(pr, dim, x, &u, gu, &lap);
                 double gN = coef_a(pr, x) * dotn(gu, n, dim); /* n . (A grad u) */
                 for (int i = 0; i < nbr; ++i) F[i] += fp.W[q] * gN * phi[i];
@@ -745,15 +794,17 @@ static int assemble_row_st(const orc_mesh *m, const orc_problem *pr, const orc_r
     /* Gauss in time with p + 1 points: exact for the degree-2p products */
     const orc_rule *gt = &ru->seg[pr_ + 1];
 
-    double *X = NULL, *W = NULL;
-    int64_t nq = vol_points(m, ru, r, pr_, &X, &W);
+    double *X = NULL, *W = NULL, *Dv = NULL, ref[3];
+    int64_t nq = vol_points(m, ru, r, pr_, &X, &W, &Dv, ref);
     if (nq < 0) return (int)nq;
+    /* points as offsets from (fan apex, t0), as in 2D */
+    const double ref3[3] = {ref[0], ref[1], sl->t0};
     for (int64_t q = 0; q < nq; ++q) {
         for (int k = 0; k < gt->n; ++k) {
             double t = sl->t0 + gt->pts[k] * tau;
             double w = W[q] * gt->w[k] * tau;
-            double x3[3] = {X[3 * q], X[3 * q + 1], t};
-            orc_basis(3, pr_, lo, hi, x3, phi, grad);
+            double d3[3] = {Dv[3 * q], Dv[3 * q + 1], gt->pts[k] * tau};
+            basis_rel(3, pr_, lo, hi, ref3, d3, phi, grad);
             double a = coef_a(pr, X + 3 * q), u, f;
             st_exact(pr, sl, X + 3 * q, t, &u, NULL, &f);
             for (int i = 0; i < nbr; ++i) {
@@ -768,12 +819,12 @@ static int assemble_row_st(const orc_mesh *m, const orc_problem *pr, const orc_r
     }
     /* time jump at t0: (U^+, W^+) on the matrix side, (U^-_{n-1}, W^+) on the load side */
     for (int64_t q = 0; q < nq; ++q) {
-        double x3[3] = {X[3 * q], X[3 * q + 1], sl->t0};
-        orc_basis(3, pr_, lo, hi, x3, phi, grad);
+        double d3[3] = {Dv[3 * q], Dv[3 * q + 1], 0.0};
+        basis_rel(3, pr_, lo, hi, ref3, d3, phi, grad);
         double uprev;
         if (sl->prev) {
             double plo[3] = {gr->lo[0], gr->lo[1], sl->tp0}, phi_[3] = {gr->hi[0], gr->hi[1], sl->t0};
-            orc_basis(3, pr_, plo, phi_, x3, phio, grado);
+            basis_rel(3, pr_, plo, phi_, ref3, d3, phio, grado);
             uprev = 0.0;
             for (int j = 0; j < nbr; ++j) uprev += sl->prev[dof_ptr[r] + j] * phio[j];
         } else {
@@ -786,6 +837,7 @@ static int assemble_row_st(const orc_mesh *m, const orc_problem *pr, const orc_r
     }
     free(X);
     free(W);
+    free(Dv);
 
     const double hst_r = sqrt(gr->diam * gr->diam + tau * tau);
     facepts fp;
@@ -825,12 +877,13 @@ static int assemble_row_st(const orc_mesh *m, const orc_problem *pr, const orc_r
             for (int k = 0; k < gt->n; ++k) {
                 double t = sl->t0 + gt->pts[k] * tau;
                 double w = fp.W[q] * gt->w[k] * tau;
-                double x3[3] = {fp.X[3 * q], fp.X[3 * q + 1], t};
-                orc_basis(3, pr_, lo, hi, x3, phi, grad);
+                const double fref[3] = {fp.ref[0], fp.ref[1], sl->t0};
+                double d3[3] = {fp.D[3 * q], fp.D[3 * q + 1], gt->pts[k] * tau};
+                basis_rel(3, pr_, lo, hi, fref, d3, phi, grad);
                 double a = coef_a(pr, fp.X + 3 * q);
                 int up = bn < 0.0;
                 if (o >= 0) {
-                    orc_basis(3, po, olo, ohi, x3, phio, grado);
+                    basis_rel(3, po, olo, ohi, fref, d3, phio, grado);
                     for (int i = 0; i < nbr; ++i) {
                         double dni = grad[3 * i] * n[0] + grad[3 * i + 1] * n[1];
                         for (int j = 0; j < nbr; ++j) {

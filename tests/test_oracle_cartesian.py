@@ -135,3 +135,25 @@ def test_cartesian_closed_form(p, coef):
     A = oracle.dense(m, pat, vals)
     R = closed_form_matrix(nx, ny, x0, x1, y0, y1, p, a, b, c)
     assert np.abs(A - R).max() <= 1e-13 * np.abs(R).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_cartesian_closed_form_small_cells_far_from_the_origin(p):
+    """Cells of 2^-13 x 2^-14 at (0.75, 0.875) (every vertex exact in binary):
+    the same closed forms to 1e-13.  A double near 0.8 is known only to ~1e-16,
+    i.e. 1e-12 of such a cell, so this pins that quadrature points enter the
+    basis through their offsets from a mesh vertex, not through their absolute
+    coordinates (which lose about three digits here)."""
+    a, b, c = 0.7, (0.8, -0.6), 1.3
+    nx, ny = 3, 2
+    hx, hy = 2.0 ** -13, 2.0 ** -14
+    x0, y0 = 0.75, 0.875
+    x1, y1 = x0 + nx * hx, y0 + ny * hy
+    m = cartesian_mesh(nx, ny, p=p, x0=x0, x1=x1, y0=y0, y1=y1)
+    assert np.array_equal(np.unique(m.x), x0 + hx * np.arange(nx + 1))
+    prob = oracle.Problem(a0=a, a1=0.0, b=(b[0], b[1], 0.0), c=c)
+    pat = oracle.pattern(m)
+    vals, _ = oracle.assemble(m, prob, pat=pat)
+    A = oracle.dense(m, pat, vals)
+    R = closed_form_matrix(nx, ny, x0, x1, y0, y1, p, a, b, c)
+    assert np.abs(A - R).max() <= 1e-13 * np.abs(R).max()
