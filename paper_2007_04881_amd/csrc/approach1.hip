@@ -78,12 +78,15 @@ __global__ void __launch_bounds__(64) k_coo_elem(A1Args A) {
             const int va = m.cell_vtx[s + 1 + t], vb = m.cell_vtx[s + 2 + t];
             const double X1 = m.x[va], Y1 = m.y[va], X2 = m.x[vb], Y2 = m.y[vb];
             const double area = 0.5 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
-            const double l0 = R_::l(3 * qi), l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
-            const double px = l0 * X0 + l1 * X1 + l2 * X2, py = l0 * Y0 + l1 * Y1 + l2 * Y2;
+            // the point as the fan apex plus an offset; box coordinates from the offset
+            const double l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
+            const double dx = l1 * (X1 - X0) + l2 * (X2 - X0), dy = l1 * (Y1 - Y0) + l2 * (Y2 - Y0);
+            const double px = X0 + dx, py = Y0 + dy;
             const double W = R_::w(qi) * area;
             const PointData pd = point_data_near(pr, tc, px, py, true);
             Eval<T, P> ev;
-            ev.at(T((px - bx.mx) * bx.cx), T((py - bx.my) * bx.cy));
+            ev.at(T(((X0 - g.lox) - (g.hix - X0) + 2.0 * dx) / (g.hix - g.lox)),
+                  T(((Y0 - g.loy) - (g.hiy - Y0) + 2.0 * dy) / (g.hiy - g.loy)));
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
                 row[i] = ev.g0[i];
@@ -178,10 +181,10 @@ __global__ void __launch_bounds__(64) k_coo_face(A1Args A) {
             const int goff = c_gl_off[NG - 1];
             const double tq = c_gl_t[goff + q];
             const double w = c_gl_w[goff + q] * len;
-            const double px = xa + tq * tx, py = ya + tq * ty;
+            const double dx = tq * tx, dy = tq * ty, px = xa + dx, py = ya + dy;
             T Lx[P + 1], dLx[P + 1], Ly[P + 1], dLy[P + 1];
-            legendre<T, P>(T((px - bL.mx) * bL.cx), Lx, dLx);
-            legendre<T, P>(T((py - bL.my) * bL.cy), Ly, dLy);
+            legendre<T, P>(T(((xa - gL.lox) - (gL.hix - xa) + 2.0 * dx) / (gL.hix - gL.lox)), Lx, dLx);
+            legendre<T, P>(T(((ya - gL.loy) - (gL.hiy - ya) + 2.0 * dy) / (gL.hiy - gL.loy)), Ly, dLy);
             const T cnx = T(bL.cx * nx), cny = T(bL.cy * ny);
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
@@ -192,8 +195,8 @@ __global__ void __launch_bounds__(64) k_coo_face(A1Args A) {
             if (Rc >= 0) {
                 const CellGeo gR = A.geo[Rc];
                 const Box bR = box_of(gR);
-                legendre<T, P>(T((px - bR.mx) * bR.cx), Lx, dLx);
-                legendre<T, P>(T((py - bR.my) * bR.cy), Ly, dLy);
+                legendre<T, P>(T(((xa - gR.lox) - (gR.hix - xa) + 2.0 * dx) / (gR.hix - gR.lox)), Lx, dLx);
+                legendre<T, P>(T(((ya - gR.loy) - (gR.hiy - ya) + 2.0 * dy) / (gR.hiy - gR.loy)), Ly, dLy);
                 const T rnx = T(bR.cx * nx), rny = T(bR.cy * ny);
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {

@@ -168,6 +168,7 @@ struct RowCtx {
     bool red;
     uint64_t gmask;
     double ex, ey, x0, y0, isq, hx, hy, pen_r;  // x0, y0: the fan apex (first vertex)
+    double lox, loy, hix, hiy, ihx, ihy;        // the box and 1 / its sides
     int64_t s0;                                 // the row's first loop entry (cell_ptr)
     int64_t pre_v, pre_d;
     Box bx;
@@ -360,10 +361,17 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
         const bool cross = edge_lane && og >= 0;
         Box bo{0.0, 0.0, 0.0, 0.0};
         double pen_o = 0.0, xsc = 0.0;
+        double olox = 0.0, oloy = 0.0, ohix = 0.0, ohiy = 0.0, oihx = 0.0, oihy = 0.0;  // the neighbour's box
         int po = P;  // degree across the edge (the row's own on the boundary)
         if (cross) {
             const CellGeo go = A.geo[og];
             bo = box_of(go);
+            olox = go.lox;
+            oloy = go.loy;
+            ohix = go.hix;
+            ohiy = go.hiy;
+            oihx = 1.0 / (go.hix - go.lox);
+            oihy = 1.0 / (go.hiy - go.loy);
             po = MX ? (int)m.cell_p[og] : P;
             pen_o = go.abar * po * po / go.h;
             xsc = R.isq / go.sqrt_box;
@@ -402,13 +410,21 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             // the lane's point and weight: a fan sub-triangle point, or point gq
             // of its edge (canonical order: lower vertex id first)
             const bool vpt = vol && !R.red;
+            // the point is (rx, ry) + (dxq, dyq) with (rx, ry) a vertex of the loop: its box
+            // coordinates come from the offset, not from absolute coordinates (which carry
+            // rounding of the size of the coordinates, large on small cells)
             double px = 0.0, py = 0.0, W = 0.0, nx = 0.0, ny = 0.0, up = 0.0, flen = 0.0;
+            double rx = 0.0, ry = 0.0, dxq = 0.0, dyq = 0.0;
             if (vpt) {
                 const int qi = q - tri * C::NQT;
                 const double area = 0.5 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
-                const double l0 = R_::l(3 * qi), l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
-                px = l0 * X0 + l1 * X1 + l2 * X2;
-                py = l0 * Y0 + l1 * Y1 + l2 * Y2;
+                const double l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
+                rx = X0;
+                ry = Y0;
+                dxq = l1 * (X1 - X0) + l2 * (X2 - X0);
+                dyq = l1 * (Y1 - Y0) + l2 * (Y2 - Y0);
+                px = X0 + dxq;
+                py = Y0 + dyq;
                 W = R_::w(qi) * area;
             } else if (epnt) {
                 const bool fwd = V1 < V2;
@@ -424,16 +440,23 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                 const int goff = c_gl_off[ngf - 1];
                 const double tq = c_gl_t[goff + gq];
                 W = c_gl_w[goff + gq] * len;
-                px = xa + tq * tx;
-                py = ya + tq * ty;
+                rx = xa;
+                ry = ya;
+                dxq = tq * tx;
+                dyq = tq * ty;
+                px = xa + dxq;
+                py = ya + dyq;
             }
+            // box coordinates ((r - lo) - (hi - r) + 2 d) / (hi - lo) of the own and the neighbour's box
+            const double xib = ((rx - R.lox) - (R.hix - rx) + 2.0 * dxq) * R.ihx;
+            const double etab = ((ry - R.loy) - (R.hiy - ry) + 2.0 * dyq) * R.ihy;
             // coefficient and load data, one evaluation for the element points
             // and the interior edge points (sin/cos by angle addition from the centre)
             PointData pdn{};
             if (vpt || (epnt && og >= 0)) pdn = point_data_near(pr, tc, px, py, SL == 0);
             if (vpt) {
-                xi = (px - bx.mx) * bx.cx;
-                eta = (py - bx.my) * bx.cy;
+                xi = xib;
+                eta = etab;
                 pc.a0 = T(W * bx.cx * bx.cx * pdn.a);
                 pc.a1 = T(W * bx.cy * bx.cy * pdn.a);
                 if (ADV) {
@@ -458,8 +481,8 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             } else if (epnt) {
                 const double w = W;
                 const double cnx = bx.cx * nx, cny = bx.cy * ny;
-                xi = (px - bx.mx) * bx.cx;
-                eta = (py - bx.my) * bx.cy;
+                xi = xib;
+                eta = etab;
                 if (og >= 0) {
                     double sigma = pr.c_sigma * (R.pen_r > pen_o ? R.pen_r : pen_o);
                     if (pr.penalty == 1) {
@@ -474,8 +497,8 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                     pc.c2 = T(hs);
                     pc.x0 = T(ha * bo.cx * nx);
                     pc.x1 = T(ha * bo.cy * ny);
-                    xin = (px - bo.mx) * bo.cx;
-                    etan = (py - bo.my) * bo.cy;
+                    xin = ((rx - olox) - (ohix - rx) + 2.0 * dxq) * oihx;
+                    etan = ((ry - oloy) - (ohiy - ry) + 2.0 * dyq) * oihy;
                 } else if (og == -1) {
                     double sigma = pr.c_sigma * R.pen_r;
                     if (pr.penalty == 1) sigma = pr.c_sigma * flen * A.pen_face[2 * m.cell_face[R.s0 + fk]];
@@ -571,13 +594,14 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             if (q < R.QR) {
                 const int qi = q - tri * C::NQT;
                 const double area = 0.5 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
-                const double l0 = R_::l(3 * qi), l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
-                const double px = l0 * X0 + l1 * X1 + l2 * X2, py = l0 * Y0 + l1 * Y1 + l2 * Y2;
+                const double l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
+                const double dxq = l1 * (X1 - X0) + l2 * (X2 - X0), dyq = l1 * (Y1 - Y0) + l2 * (Y2 - Y0);
+                const double px = X0 + dxq, py = Y0 + dyq;
                 const PointData pd = point_data_near(pr, tc, px, py, true);
                 const T wf = T(R_::w(qi) * area * pd.f);
                 T Lx[P + 1], dLx[P + 1], Ly[P + 1], dLy[P + 1];
-                legendre<T, P>(T((px - bx.mx) * bx.cx), Lx, dLx);
-                legendre<T, P>(T((py - bx.my) * bx.cy), Ly, dLy);
+                legendre<T, P>(T(((X0 - R.lox) - (R.hix - X0) + 2.0 * dxq) * R.ihx), Lx, dLx);
+                legendre<T, P>(T(((Y0 - R.loy) - (R.hiy - Y0) + 2.0 * dyq) * R.ihy), Ly, dLy);
 #pragma unroll
                 for (int i = 0; i < NB; ++i) acc[ED + i] = fmat(wf, Lx[exp_a(i)] * Ly[exp_b(i)], acc[ED + i]);
             }
@@ -713,6 +737,12 @@ __device__ __forceinline__ void row_body(const AsmArgs &A, const int c, T *wlds)
     R.tc.cy = uniform(R.tc.cy);
     R.tc.near = __builtin_amdgcn_readfirstlane(R.tc.near);
     R.pen_r = uniform(g.abar * P * P / g.h);
+    R.lox = uniform(g.lox);
+    R.loy = uniform(g.loy);
+    R.hix = uniform(g.hix);
+    R.hiy = uniform(g.hiy);
+    R.ihx = uniform(1.0 / (g.hix - g.lox));
+    R.ihy = uniform(1.0 / (g.hiy - g.loy));
     R.s0 = s;
     R.red = A.reduced && A.qr_ok[c];
     R.QM = R.red ? kQrNodes : (nv - 2) * C::NQT;  // points of the element matrix

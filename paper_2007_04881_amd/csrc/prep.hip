@@ -153,8 +153,9 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
             loy = fmin(loy, yi);
             hix = fmax(hix, xi);
             hiy = fmax(hiy, yi);
-            const double2 vn = s_xy[grp][i + 1 == nv ? 0 : i + 1];
-            a2 += xi * vn.y - vn.x * yi;
+            // shoelace about the first vertex: products of exact coordinate differences
+            const double2 vn = s_xy[grp][i + 1 == nv ? 0 : i + 1], v0 = s_xy[grp][0];
+            a2 += (xi - v0.x) * (vn.y - v0.y) - (vn.x - v0.x) * (yi - v0.y);
             for (int j = i + 1; j < nv; ++j) {
                 const double2 vj = s_xy[grp][j];
                 const double dx = xi - vj.x, dy = yi - vj.y;

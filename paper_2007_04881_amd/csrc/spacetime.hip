@@ -118,7 +118,8 @@ __global__ void __launch_bounds__(64) k_row_st(StArgs A) {
     const CellGeo g = A.geo[c];
     const Box bx = box_of(g);
     const TrigCentre tc = trig_centre_of(g);
-    const double tau = sl.t1 - sl.t0, ct = 2.0 / tau, tmid = 0.5 * (sl.t0 + sl.t1);
+    const double tau = sl.t1 - sl.t0, ct = 2.0 / tau;
+    const double ihx = 1.0 / (g.hix - g.lox), ihy = 1.0 / (g.hiy - g.loy);
     const double hst = sqrt(g.h * g.h + tau * tau);
     const double pen_r = g.abar * P * P / hst;
     const int64_t blk0 = A.row_ptr[c];  // the row's first block (uniform degree: values at k NB^2)
@@ -172,15 +173,20 @@ __global__ void __launch_bounds__(64) k_row_st(StArgs A) {
             for (int k = 0; k < W; ++k) row[k] = T(0);
             if (vol || bot) {
                 const double area = 0.5 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
-                const double l0 = R_::l(3 * qi), l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
-                const double px = l0 * X0 + l1 * X1 + l2 * X2, py = l0 * Y0 + l1 * Y1 + l2 * Y2;
+                // the point as the fan apex plus an offset, and t0 plus an offset in time:
+                // box coordinates from the offsets
+                const double l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
+                const double dx = l1 * (X1 - X0) + l2 * (X2 - X0), dy = l1 * (Y1 - Y0) + l2 * (Y2 - Y0);
+                const double px = X0 + dx, py = Y0 + dy;
                 const double wx = R_::w(qi) * area;
                 const PointData pd = point_data_near(pr, tc, px, py, vol);
                 const int goff = c_gl_off[NT - 1];
-                const double t = vol ? sl.t0 + c_gl_t[goff + kt] * tau : sl.t0;
+                const double tr = vol ? c_gl_t[goff + kt] : 0.0;  // (t - t0) / tau
+                const double t = sl.t0 + tr * tau;
                 const double w = vol ? wx * c_gl_w[goff + kt] * tau : wx;
                 StEval<T, P> ev;
-                ev.at(T((px - bx.mx) * bx.cx), T((py - bx.my) * bx.cy), T((t - tmid) * ct));
+                ev.at(T(((X0 - g.lox) - (g.hix - X0) + 2.0 * dx) * ihx),
+                      T(((Y0 - g.loy) - (g.hiy - Y0) + 2.0 * dy) * ihy), T(2.0 * tr - 1.0));
                 if (vol) {
                     const double Tt = 1.0 + sl.tau1 * t + sl.tau2 * t * t, dTt = sl.tau1 + 2.0 * sl.tau2 * t;
                     const T cxw = T(bx.cx), cyw = T(bx.cy);
@@ -203,8 +209,8 @@ __global__ void __launch_bounds__(64) k_row_st(StArgs A) {
                         // the previous slab's solution at its top (t0): P_c(1) = 1 in its box
                         constexpr StIdx I = make_st_idx<P>();
                         T Lx[P + 1], dLx[P + 1], Ly[P + 1], dLy[P + 1];
-                        legendre<T, P>(T((px - bx.mx) * bx.cx), Lx, dLx);
-                        legendre<T, P>(T((py - bx.my) * bx.cy), Ly, dLy);
+                        legendre<T, P>(T(((X0 - g.lox) - (g.hix - X0) + 2.0 * dx) * ihx), Lx, dLx);
+                        legendre<T, P>(T(((Y0 - g.loy) - (g.hiy - Y0) + 2.0 * dy) * ihy), Ly, dLy);
                         const double taup = sl.t0 - sl.tp0;
                         const double sp = 1.0 / (g.sqrt_box * sqrt(taup));
                         uprev = 0.0;
@@ -294,11 +300,13 @@ __global__ void __launch_bounds__(64) k_row_st(StArgs A) {
                 const double up = bn < 0.0 ? bn : 0.0;
                 const int goe = c_gl_off[NGE - 1], got = c_gl_off[NT - 1];
                 const double te = c_gl_t[goe + kg];
-                const double px = xa + te * tx, py = ya + te * ty;
-                const double t = sl.t0 + c_gl_t[got + kt] * tau;
+                const double dx = te * tx, dy = te * ty, px = xa + dx, py = ya + dy;
+                const double tr = c_gl_t[got + kt];
+                const double t = sl.t0 + tr * tau;
                 const double w = c_gl_w[goe + kg] * len * c_gl_w[got + kt] * tau;
                 StEval<T, P> ev;
-                ev.at(T((px - bx.mx) * bx.cx), T((py - bx.my) * bx.cy), T((t - tmid) * ct));
+                ev.at(T(((xa - g.lox) - (g.hix - xa) + 2.0 * dx) * ihx),
+                      T(((ya - g.loy) - (g.hiy - ya) + 2.0 * dy) * ihy), T(2.0 * tr - 1.0));
                 const T cnx = T(bx.cx * nx), cny = T(bx.cy * ny);
                 T dn[NB];
 #pragma unroll
@@ -320,7 +328,8 @@ __global__ void __launch_bounds__(64) k_row_st(StArgs A) {
                         row[4 * NB + i] = ga * ev.v[i];
                     }
                     StEval<T, P> eo;
-                    eo.at(T((px - bo.mx) * bo.cx), T((py - bo.my) * bo.cy), T((t - tmid) * ct));
+                    eo.at(T(((xa - go.lox) - (go.hix - xa) + 2.0 * dx) / (go.hix - go.lox)),
+                          T(((ya - go.loy) - (go.hiy - ya) + 2.0 * dy) / (go.hiy - go.loy)), T(2.0 * tr - 1.0));
                     const T onx = T(bo.cx * nx), ony = T(bo.cy * ny);
                     const T bx_ = T((-sigma + up) * w), gx_ = T(0.5 * a * w);
 #pragma unroll

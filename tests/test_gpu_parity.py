@@ -388,3 +388,20 @@ def test_single_persistent_launch_over_all_bins(precision):
     torch.cuda.synchronize()
     assert torch.equal(v3, outs[1][0]) and torch.equal(r3, outs[1][1])
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_cells_far_from_the_origin(precision):
+    """Cells of size ~1e-4 near (0.7, 0.8), degrees 1..4, variable a with
+    advection: quadrature points enter the basis through their offsets from a
+    mesh vertex on both sides, so FP64 agrees to 1e-12 although absolute
+    coordinates carry rounding of ~1e-12 of a cell."""
+    import copy
+    m = voronoi_mesh(400, 89, lloyd=1, p=1)
+    m = m.with_degrees(np.random.default_rng(15).integers(1, 5, m.n_cells))
+    t = copy.deepcopy(m)
+    t.x = 0.7 + 2.0 ** -12 * m.x
+    t.y = 0.8 + 2.0 ** -12 * m.y
+    t.name = m.name + "_small"
+    _case(t, DAR, precision)
+    _case(t, dict(DAR, penalty="covering"), precision)
