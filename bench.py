@@ -281,13 +281,16 @@ def mixed_degree_study(D, torch, steps, warmup):
         ctx.run(params, prec, vals, rhs)
         asm_t = ctx.time_kernels(10)[1]
         vb = 4 if prec == D.F32 else 8
+        tname = "float" if prec == D.F32 else "double"
+        row = choice[1 if prec == D.F32 else 0]
+        fused = bool(row[0])
+        kname = (f"k_row2d_fused<{tname},false> (one persistent launch over every bin)" if fused else
+                 f"k_row2d<{tname},p,4,true,false,*> (one launch per degree, summed)")
         out[name] = {"ms_per_step": ms, "block_nnz_per_s": info.nnzb / (ms * 1e-3),
                      "kernel_ms": {"prep": prep_ms, "assemble": asm_ms},
-                     "autotuned": {"launch_cfg_by_degree": choice[1 if prec == D.F32 else 0][1:],
+                     "autotuned": {"single_launch": fused, "launch_cfg_by_degree": row[1:],
                                    "ms_per_step": ms_t, "assemble_kernel_ms": asm_t},
-                     "roofline": roofline_hbm(algorithmic_bytes(mesh, info, vb), asm_t,
-                                              f"k_row2d<{'float' if prec == D.F32 else 'double'},p,4,true,false,*> "
-                                              f"(one launch per degree, summed)")}
+                     "roofline": roofline_hbm(algorithmic_bytes(mesh, info, vb), asm_t, kname)}
         del vals, rhs
     ctx.close()
     return out
@@ -401,24 +404,42 @@ def spacetime_study(D, torch, steps, warmup):
     return out
 
 
-def traffic_probe(D, torch):
-    """A short program for rocprofv3 --pmc: the assembly kernel's dispatches and
-    a copy of known size to scale the counters by."""
+def traffic_probe(D, torch, which="voronoi16384"):
+    """A short program for rocprofv3 --pmc: a workload's assembly dispatches and
+    a copy of known size to scale the counters by.
+      voronoi16384  10 steps (FP32) of the 16,384-cell workload, 10 more in each
+                    of the four launch configurations (cfg = r + 2 s: register
+                    budget r, row order s);
+      mixed262144   the 262,144-cell mixed-degree mesh, FP32: 5 steps with one
+                    launch per degree, then 5 with the single persistent launch;
+      kuhn128       the 32,768-polyhedron mesh, 5 FP32 steps, then 5 FP64."""
     from meshgen import config_mesh, problem_params
-    mesh, params = config_mesh(2), problem_params(2)
+    k = {"voronoi16384": 2, "mixed262144": 3, "kuhn128": 4}[which]
+    mesh, params = config_mesh(k), problem_params(k)
     ctx = D.Context(0)
     ctx.upload(mesh)
     ctx.pattern()
-    vals, rhs = ctx.outputs(D.F32)
-    for _ in range(10):
-        ctx.run(params, D.F32, vals, rhs)
-    # 10 steps in each launch configuration, in order (register budget r, row
-    # order s: cfg = r + 2 s); the counter summary maps dispatches to them
-    for cfg in range(4):
-        ctx.set_launch(D.F32, 2, cfg)
+    if which == "voronoi16384":
+        vals, rhs = ctx.outputs(D.F32)
         for _ in range(10):
             ctx.run(params, D.F32, vals, rhs)
+        for cfg in range(4):
+            ctx.set_launch(D.F32, 2, cfg)
+            for _ in range(10):
+                ctx.run(params, D.F32, vals, rhs)
+    elif which == "mixed262144":
+        vals, rhs = ctx.outputs(D.F32)
+        for fused in (0, 1):
+            ctx.set_launch(D.F32, 0, fused)
+            for _ in range(5):
+                ctx.run(params, D.F32, vals, rhs)
+    else:
+        for prec in (D.F32, D.F64):
+            vals, rhs = ctx.outputs(prec)
+            for _ in range(5):
+                ctx.run(params, prec, vals, rhs)
     torch.cuda.synchronize()
+    del vals, rhs
     x = torch.empty(16 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 64 MiB
     y = torch.empty_like(x)
     x.fill_(1.0)
@@ -426,7 +447,7 @@ def traffic_probe(D, torch):
         y.copy_(x)
     torch.cuda.synchronize()
     ctx.close()
-    log("traffic probe done")
+    log(f"traffic probe {which} done")
 
 
 def main():
@@ -439,9 +460,10 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the polyhedral (3D) workload")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree 262,144-cell workload")
     ap.add_argument("--no-extras", action="store_true", help="skip the Approach-1 and space-time studies")
-    ap.add_argument("--traffic-probe", action="store_true",
-                    help="for HBM counter runs: 10 whole steps of the headline workload, 10 more in each of the "
-                         "four launch configurations, then 10 copies of a "
+    ap.add_argument("--traffic-probe", nargs="?", const="voronoi16384", default=None,
+                    choices=["voronoi16384", "mixed262144", "kuhn128"],
+                    help="for HBM counter runs: a few whole steps of one workload (default the headline one, "
+                         "in each of its four launch configurations), then 10 copies of a "
                          "64 MiB tensor (the copy calibrates FETCH_SIZE / WRITE_SIZE); prints no JSON")
     ap.add_argument("--train-polygons", type=int, default=1_000_000)
     ap.add_argument("--train-epochs", type=int, default=30)
@@ -457,7 +479,7 @@ def main():
     from meshgen import config_mesh, problem_params
 
     if args.traffic_probe:
-        traffic_probe(D, torch)
+        traffic_probe(D, torch, args.traffic_probe)
         return
 
     log("16,384-cell mesh")

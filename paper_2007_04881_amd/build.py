@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgpoly.so")
-SOURCES = ["runtime.hip", "learned_rt.hip", "prep.hip", "assemble_row.hip", "prep3d.hip", "assemble3d.hip",
+SOURCES = ["runtime.hip", "learned_rt.hip", "prep.hip", "assemble_row.hip", "assemble_f32.hip", "prep3d.hip", "assemble3d.hip",
            "qrule.hip", "mlp.hip", "approach1.hip", "approach1_rt.hip", "spacetime.hip", "spacetime_rt.hip"]
 ARCH = os.environ.get("DGP_OFFLOAD_ARCH", "gfx950")
 

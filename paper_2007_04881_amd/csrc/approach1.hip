@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(64) k_coo_face(A1Args A) {
                 if (pr.penalty == 1)
                     sigma = pr.c_sigma * len * fmax(A.pen_face[2 * f], A.pen_face[2 * f + 1]);
                 else
-                    sigma = pr.c_sigma * fmax(gL.abar * P * P / gL.h, gR.abar * P * P / gR.h);
+                    sigma = pr.c_sigma * fmax(gL.pen, gR.pen);
                 const double upL = bn < 0.0 ? bn : 0.0, upR = -bn < 0.0 ? -bn : 0.0;
                 // blocks (test side X, trial side Y): LL, LR, RL, RR; s_L = 1, s_R = -1
                 const double ha = 0.5 * a * w;
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(64) k_coo_face(A1Args A) {
                 if (bc == 1) {
                     const PointData pd = point_data(pr, px, py, false);
                     const double sigma = pr.penalty == 1 ? pr.c_sigma * len * A.pen_face[2 * f]
-                                                         : pr.c_sigma * gL.abar * P * P / gL.h;
+                                                         : pr.c_sigma * gL.pen;
                     const double up = bn < 0.0 ? bn : 0.0;
                     cf[0] = T(-pd.a * w), cf[1] = T((sigma - up) * w), cf[2] = T(-pd.a * w);
                     cf[12] = T(-pd.a * w * pd.u);          // times dn_i

@@ -59,10 +59,13 @@ __device__ __forceinline__ Box box_of(const CellGeo &g) {
     Box b;
     b.mx = 0.5 * (g.lox + g.hix);
     b.my = 0.5 * (g.loy + g.hiy);
-    b.cx = 2.0 / (g.hix - g.lox);
-    b.cy = 2.0 / (g.hiy - g.loy);
+    b.cx = 2.0 * g.ihx;  // = 2 / (hix - lox) exactly (scaling by 2 commutes with rounding)
+    b.cy = 2.0 * g.ihy;
     return b;
 }
+
+// sqrt(2a + 1): the normalisation of the one-dimensional Legendre factor of degree a
+constexpr double kSqrt2a1[kMaxP + 1] = {1.0, 1.7320508075688772, 2.23606797749979, 2.6457513110645907, 3.0};
 
 // sqrt((2a+1)(2b+1)) of basis function i: its normalisation times sqrt(|B|)
 // the same as compile-time constants (for unrolled indices)

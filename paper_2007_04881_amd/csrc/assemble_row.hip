@@ -43,6 +43,7 @@
 
 #include "asm_common.h"
 #include "kernels.h"
+#include "row_common.h"
 #include "wave.h"
 
 namespace dgp {
@@ -75,18 +76,22 @@ struct RowCfg {
     // cross blocks through a per-wave LDS table (XL) instead of per-column group sums
     static constexpr bool XL = sizeof(T) == 4 && P <= 2 && PN <= 2;
     static constexpr int XW = 3 * (NB + NBN);  // table row per lane: test terms, then trial terms
+    // EL: the element block and the load through a transposed per-wave LDS table
+    // (rows: the test terms of each basis function, the trial terms, the load
+    // terms; columns k = 3 (lane) + a), each lane forming one entry as a dot
+    // product over the pass's points, instead of 42 register accumulators per lane
+    // and a reduce-scatter across the wave (FP32, p = 2 rows among p = 2 neighbours)
+    static constexpr bool EL = XL && P == 2 && PN == 2;
+    static constexpr int KS = 3 * 64 + 4;  // row stride: 192 point terms + 4 (rows start 4 banks apart)
     // CM: cross blocks on the matrix cores (p >= 3, and the FP32 mixed-degree
     // kernels, whose neighbours may have larger blocks than the row's own; in
     // FP64 the staged trial terms cost those kernels a wave per SIMD: slower)
     static constexpr bool CM = !XL && (P >= 3 || (PN > P && sizeof(T) == 4));
     static constexpr int CMW = 2 * 3 * FG * 16;  // its table per wave (T elements)
     // one LDS region per wave serves every table (their phases are separated by wave barriers)
-    static constexpr int LW0 = XL ? 64 * XW : 0, LW1 = MF ? MFW : 0, LW2 = CM ? CMW : 0;
+    static constexpr int LW0 = EL ? (2 * NB + 1) * KS : XL ? 64 * XW : 0, LW1 = MF ? MFW : 0, LW2 = CM ? CMW : 0;
     static constexpr int LW = LW0 > LW1 ? (LW0 > LW2 ? LW0 : LW2) : (LW1 > LW2 ? LW1 : LW2);
 };
-
-// sqrt(2a + 1): the normalisation of the one-dimensional Legendre factor of degree a
-constexpr double kSqrt2a1[kMaxP + 1] = {1.0, 1.7320508075688772, 2.23606797749979, 2.6457513110645907, 3.0};
 
 
 // Per-point coefficients of the rank-3 updates (see the file comment).
@@ -248,6 +253,133 @@ __device__ __forceinline__ void cross_lds(const AsmArgs &A, const RowCtx &R, con
     wave_sync();  // the table is rewritten by the next point set
 }
 
+// The transposed table of the EL kernels, per wave: row i < NB holds the
+// normalised test terms u_a(i) at column k = 3 (lane) + a; rows NB .. 2 NB - 1
+// first hold the neighbour's trial terms s_a(j) (cross blocks), then the row's
+// own trial terms t_a(j) (element block); row 2 NB the load terms r_a.  Every
+// lane writes its point's columns (lanes without a point have zero
+// coefficients, so their trial and load terms are zero).
+//
+// Cross blocks: each lane takes entries (group, i, j) of the pass and sums the
+// 3 FG columns of its group's lanes: u(i) . s(j), written in row-major order.
+template <typename T, int P, int PN>
+__device__ __forceinline__ void cross_el(const AsmArgs &A, const RowCtx &R, const Eval<T, P> &ev,
+                                         const PointCoef<T> &pc, double xin, double etan, double xsc, int base,
+                                         int d, int og, int gvoff, int fk) {
+    using C = RowCfg<T, P, PN>;
+    constexpr int NB = C::NB, NBN = C::NBN, FG = C::FG, NBX = NB * NBN, KS = C::KS;
+    constexpr int NGP = C::NG;  // Gauss points per edge (all neighbours have degree P here)
+    static_assert(NGP <= FG, "one edge point per lane of a group");
+    T *U = static_cast<T *>(R.xs), *S = U + NB * KS;
+    const int k0 = 3 * R.lane;
+    {
+        T Lx[PN + 1], dLx[PN + 1], Ly[PN + 1], dLy[PN + 1];
+        legendre<T, PN>(T(xin), Lx, dLx);
+        legendre<T, PN>(T(etan), Ly, dLy);
+#pragma unroll
+        for (int a = 1; a <= PN; ++a) {
+            Lx[a] *= T(kSqrt2a1[a]);
+            dLx[a] *= T(kSqrt2a1[a]);
+            Ly[a] *= T(kSqrt2a1[a]);
+            dLy[a] *= T(kSqrt2a1[a]);
+        }
+        const T xs_ = T(xsc);
+        const T sb0 = -pc.b0 * xs_, sb1 = -pc.b1 * xs_, sx0 = pc.x0 * xs_, sx1 = pc.x1 * xs_, sc2 = -pc.c2 * xs_;
+#pragma unroll
+        for (int j = 0; j < NBN; ++j) {
+            const T vj = Lx[exp_a(j)] * Ly[exp_b(j)];
+            const T gj0 = dLx[exp_a(j)] * Ly[exp_b(j)], gj1 = Lx[exp_a(j)] * dLy[exp_b(j)];
+            S[j * KS + k0] = sb0 * vj;
+            S[j * KS + k0 + 1] = sb1 * vj;
+            S[j * KS + k0 + 2] = fmat(sx0, gj0, fmat(sx1, gj1, sc2 * vj));
+        }
+    }
+    wave_sync();
+    // groups whose lanes lie in this pass (groups never straddle passes: 64 % FG == 0)
+    const int gfirst = base > R.QF0 ? (base - R.QF0) / FG : 0;
+    const int glast = min(R.ng, (base + 64 - R.QF0) / FG);
+    const int nent = (glast - gfirst) * NBX;
+    T *__restrict__ vals = static_cast<T *>(A.vals);
+    for (int e0 = 0; e0 < nent; e0 += 64) {
+        const int e = min(e0 + R.lane, nent - 1);
+        const int gl = e / NBX, r = e - gl * NBX, i = r / NBN, j = r - i * NBN;
+        const int ql = R.QF0 + (gfirst + gl) * FG - base;  // the group's first lane (a multiple of 4)
+        const int oge = __shfl(og, ql, 64), gvo = __shfl(gvoff, ql, 64), fke = __shfl(fk, ql, 64);
+        const T *uu = U + i * KS + 3 * ql;
+        const T *ss = S + j * KS + 3 * ql;
+        T sum = T(0);
+#pragma unroll
+        for (int t = 0; t < 3 * NGP; ++t) sum = fmat(uu[t], ss[t], sum);
+        if (e0 + R.lane < nent && oge >= 0 && fke >= 0) {
+            T *dst = vals + R.pre_v + gvo + i * NBN + j;
+            if (d == 0)
+                *dst = sum;
+            else
+                *dst += sum;
+        }
+    }
+}
+
+// Writes the lane's normalised test terms (columns 3 lane .. 3 lane + 2 of rows 0 .. NB - 1).
+template <typename T, int P, int PN>
+__device__ __forceinline__ void el_test_terms(const RowCtx &R, const Eval<T, P> &ev) {
+    using C = RowCfg<T, P, PN>;
+    constexpr int NB = C::NB, KS = C::KS;
+    T *U = static_cast<T *>(R.xs);
+    const int k0 = 3 * R.lane;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        U[i * KS + k0] = ev.g0[i] * T(kNorm[i]);
+        U[i * KS + k0 + 1] = ev.g1[i] * T(kNorm[i]);
+        U[i * KS + k0 + 2] = ev.v[i] * T(kNorm[i]);
+    }
+}
+
+// Element block and load of the pass: the lane's trial terms t_a(j) and load
+// terms r_a go to rows NB .. 2 NB; then lane e < NB (NB + 1) adds entry
+// (i, j) = (e / (NB + 1), e mod (NB + 1)) (j = NB: the load of row i) over the
+// columns of the pass's np points to its accumulator.  load_only: only the load
+// entries take part (the trial rows are not written).
+template <typename T, int P, int PN>
+__device__ __forceinline__ void elem_el(const RowCtx &R, const Eval<T, P> &ev, const PointCoef<T> &pc, int np,
+                                        bool load_only, T &acc_e) {
+    using C = RowCfg<T, P, PN>;
+    constexpr int NB = C::NB, KS = C::KS;
+    T *U = static_cast<T *>(R.xs), *Tt = U + NB * KS, *Rr = U + 2 * NB * KS;
+    const int k0 = 3 * R.lane;
+    if (!load_only) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            Tt[j * KS + k0] = fmat(pc.a0, ev.g0[j], pc.b0 * ev.v[j]);
+            Tt[j * KS + k0 + 1] = fmat(pc.a1, ev.g1[j], pc.b1 * ev.v[j]);
+            Tt[j * KS + k0 + 2] = fmat(pc.c0, ev.g0[j], fmat(pc.c1, ev.g1[j], pc.c2 * ev.v[j]));
+        }
+    }
+    Rr[k0] = pc.r0;
+    Rr[k0 + 1] = pc.r1;
+    Rr[k0 + 2] = pc.r2;
+    wave_sync();
+    const int i = R.lane / (NB + 1), j = R.lane - (NB + 1) * i;
+    if (R.lane < NB * (NB + 1) && (!load_only || j == NB)) {
+        const float4 *uu = reinterpret_cast<const float4 *>(U + i * KS);
+        const float4 *tt = reinterpret_cast<const float4 *>(j < NB ? Tt + j * KS : Rr);
+        const int n4 = (3 * np + 3) >> 2;  // columns of the pass's points, in fours
+        T s0 = T(0), s1 = T(0);
+        int k = 0;
+        for (; k + 1 < n4; k += 2) {
+            const float4 a = uu[k], b = tt[k], c = uu[k + 1], e = tt[k + 1];
+            s0 = fmat(a.x, b.x, fmat(a.y, b.y, fmat(a.z, b.z, fmat(a.w, b.w, s0))));
+            s1 = fmat(c.x, e.x, fmat(c.y, e.y, fmat(c.z, e.z, fmat(c.w, e.w, s1))));
+        }
+        if (k < n4) {
+            const float4 a = uu[k], b = tt[k];
+            s0 = fmat(a.x, b.x, fmat(a.y, b.y, fmat(a.z, b.z, fmat(a.w, b.w, s0))));
+        }
+        acc_e += s0 + s1;
+    }
+    wave_sync();  // the table is rewritten by the next point set
+}
+
 // Cross blocks on the matrix cores (the p >= 3 and mixed-degree kernels): one edge group at a
 // time, its FG lanes write 3 rows each of normalised test terms u_a(i) and of
 // the neighbour's trial terms s_a(j) (normalised, scaled by its box factor;
@@ -347,6 +479,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
     T acc[64];
 #pragma unroll
     for (int e = 0; e < 64; ++e) acc[e] = T(0);  // [0, ED): element block slice, [ED, ED + NB): load
+    T acc_e = T(0);                              // EL kernels: the lane's entry of the element block or load
     MfAcc<T> accm = {T(0), T(0), T(0), T(0)};   // MF kernels: the element block on the matrix cores
 
     for (int base = 0; base < Qtot; base += 64) {
@@ -370,11 +503,11 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             oloy = go.loy;
             ohix = go.hix;
             ohiy = go.hiy;
-            oihx = 1.0 / (go.hix - go.lox);
-            oihy = 1.0 / (go.hiy - go.loy);
+            oihx = go.ihx;
+            oihy = go.ihy;
             po = MX ? (int)m.cell_p[og] : P;
-            pen_o = go.abar * po * po / go.h;
-            xsc = R.isq / go.sqrt_box;
+            pen_o = go.pen;  // abar p^2 / h at the neighbour's degree
+            xsc = R.isq * go.isq;
         }
         const int nbo = nb2d(po);
         const int ngf = (P > po ? P : po) + 1 > 3 ? (P > po ? P : po) + 1 : 3;  // this edge's Gauss points
@@ -521,7 +654,7 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
             ev.at(T(xi), T(eta));
             if constexpr (C::MF) mf_element<T, P>(static_cast<T *>(R.xs), lane, ev, pc, accm);
 #pragma unroll
-            for (int jj = 0; jj < (C::MF ? 0 : JS); ++jj) {
+            for (int jj = 0; jj < (C::MF || C::EL ? 0 : JS); ++jj) {
                 const int j = j0 + jj;
                 if (j < NB) {
                     const T t0 = fmat(pc.a0, ev.g0[j], pc.b0 * ev.v[j]);
@@ -532,12 +665,19 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                         acc[i * JS + jj] = fmat(ev.g0[i], t0, fmat(ev.g1[i], t1, fmat(ev.v[i], t2, acc[i * JS + jj])));
                 }
             }
-            if (SL == 0) {
+            if (SL == 0 && !C::EL) {
 #pragma unroll
                 for (int i = 0; i < NB; ++i)
                     acc[ED + i] = fmat(ev.g0[i], pc.r0, fmat(ev.g1[i], pc.r1, fmat(ev.v[i], pc.r2, acc[ED + i])));
             }
-            if constexpr (C::XL) {
+            if constexpr (C::EL) {
+                el_test_terms<T, P, PN>(R, ev);
+                if (pass_has_edges) {
+                    cross_el<T, P, PN>(A, R, ev, pc, xin, etan, xsc, base, d, og, gvoff, fk);
+                    wave_sync();  // cross entries read before the trial rows are rewritten
+                }
+                elem_el<T, P, PN>(R, ev, pc, min(64, Qtot - base), false, acc_e);
+            } else if constexpr (C::XL) {
                 if (pass_has_edges) cross_lds<T, P, PN>(A, R, ev, pc, xin, etan, xsc, base, d, og, gvoff, fk);
             } else if constexpr (C::CM) {
                 if (pass_has_edges) cross_mf<T, P, PN>(A, R, ev, pc, xin, etan, xsc, base, d, og, gvoff, fk, nbo);
@@ -584,7 +724,33 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
         }
     }
     // load-only points of rows with a reduced rule (fan sub-triangles)
-    if (SL == 0) {
+    if constexpr (C::EL) {
+        for (int base = 0; base < R.QR; base += 64) {
+            const int q = base + lane;
+            const bool in = q < R.QR;
+            const int tri = in ? q / C::NQT : 0;
+            const double X0 = R.x0, Y0 = R.y0;
+            const double X1 = __shfl(ex, tri + 1, 64), Y1 = __shfl(ey, tri + 1, 64);
+            const double X2 = __shfl(ex, tri + 2, 64), Y2 = __shfl(ey, tri + 2, 64);
+            PointCoef<T> pc;
+            pc.zero();
+            double xi = 0.0, eta = 0.0;
+            if (in) {
+                const int qi = q - tri * C::NQT;
+                const double area = 0.5 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
+                const double l1 = R_::l(3 * qi + 1), l2 = R_::l(3 * qi + 2);
+                const double dxq = l1 * (X1 - X0) + l2 * (X2 - X0), dyq = l1 * (Y1 - Y0) + l2 * (Y2 - Y0);
+                const PointData pd = point_data_near(pr, tc, X0 + dxq, Y0 + dyq, true);
+                pc.r2 = T(R_::w(qi) * area * pd.f);
+                xi = ((X0 - R.lox) - (R.hix - X0) + 2.0 * dxq) * R.ihx;
+                eta = ((Y0 - R.loy) - (R.hiy - Y0) + 2.0 * dyq) * R.ihy;
+            }
+            Eval<T, P> ev;
+            ev.at(T(xi), T(eta));
+            el_test_terms<T, P, PN>(R, ev);
+            elem_el<T, P, PN>(R, ev, pc, min(64, R.QR - base), true, acc_e);
+        }
+    } else if (SL == 0) {
         for (int base = 0; base < R.QR; base += 64) {
             const int q = base + lane;
             const int tri = q < R.QR ? q / C::NQT : 0;
@@ -606,6 +772,18 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
                 for (int i = 0; i < NB; ++i) acc[ED + i] = fmat(wf, Lx[exp_a(i)] * Ly[exp_b(i)], acc[ED + i]);
             }
         }
+    }
+    if constexpr (C::EL) {
+        // lane e < NB (NB + 1) holds entry (i, j) = (e / (NB + 1), e mod (NB + 1)),
+        // the test normalisation applied (j = NB: the load of row i)
+        const int i = lane / (NB + 1), j = lane - (NB + 1) * i;
+        if (lane < NB * (NB + 1)) {
+            if (j < NB)
+                vals[R.pre_v + R.dvoff + i * NB + j] = T(double(acc_e) * (c_norm[j] * R.isq * R.isq));
+            else
+                rhs[R.pre_d + i] = T(double(acc_e) * R.isq);
+        }
+        return;
     }
     // element block slice and load: reduce-scatter over the wave, lane e writes entry e
     WaveRS<T, 32, (SL == 0 ? C::E : ED)>::run(acc, lane);
@@ -643,80 +821,11 @@ template <typename T, int P, int PN, bool MX, bool ADV>
 __device__ __forceinline__ void row_body(const AsmArgs &A, const int c, T *wlds) {
     using C = RowCfg<T, P, PN>;
     constexpr int NB = C::NB, FG = C::FG;
-    const DevMesh &m = A.m;
     const int lane = threadIdx.x & 63;
-    const int64_t s = m.cell_ptr[c];
-    const int nv = (int)(m.cell_ptr[c + 1] - s);
-
-    // ---- the row's offsets (scanned tile sums plus the element's prefix inside its tile)
-    const int t0 = c / kPrepTile;
-    const int4 cr = reinterpret_cast<const int4 *>(A.cnt)[c];
-    int64_t tb, tv, td;  // the tile's offsets
-    if (A.tile_sum) {
-        // no scan kernel ran: sum the sums of the tiles before this one (at most
-        // kInlineTiles of them; with at most 24 edges per polygon every prefix
-        // stays far below 2^31)
-        int sb = 0, sv = 0, sd = 0;
-        for (int t = lane; t < t0; t += 64) {
-            const int4 v = A.tile_sum[t];
-            sb += v.x;
-            sv += v.y;
-            sd += v.z;
-        }
-        tb = __builtin_amdgcn_readfirstlane(wave_sum_i(sb));
-        tv = __builtin_amdgcn_readfirstlane(wave_sum_i(sv));
-        td = __builtin_amdgcn_readfirstlane(wave_sum_i(sd));
-    } else {
-        tb = A.tile_off[3 * t0];
-        tv = A.tile_off[3 * t0 + 1];
-        td = A.tile_off[3 * t0 + 2];
-    }
-    const int64_t pre_b = tb + cr.x;
-    const int64_t pre_v = tv + cr.y;
-    const int64_t pre_d = td + cr.z;
-    const int drank = cr.w & 255, dvoff = cr.w >> 8;
-
-    // ---- loop edges, one per lane
-    int vid = 0, o = -3, rank = 0, voff = 0, dupc = 0;
-    bool first = false;
-    double ex = 0.0, ey = 0.0;
-    if (lane < nv) {
-        const EdgeRec er = A.erec[s + lane];
-        ex = er.x;
-        ey = er.y;
-        vid = er.vid;
-        o = er.o;
-        first = (er.rank & kEdgeFirst) != 0;
-        rank = er.rank & 255;
-        dupc = (er.rank >> kEdgeDupShift) & 255;
-        voff = er.voff;
-    }
-    const uint64_t fm = __ballot(first);
-    if (A.write_pattern) {
-        if (first) {
-            A.col_idx[pre_b + rank] = o;
-            A.val_ptr[pre_b + rank] = pre_v + voff;
-        }
-        if (lane == 0) {
-            A.col_idx[pre_b + drank] = c;
-            A.val_ptr[pre_b + drank] = pre_v + dvoff;
-            A.row_ptr[c] = pre_b;
-            A.dof_ptr[c] = pre_d;
-            if (c == m.n_cells - 1) {
-                const int n_tiles = (m.n_cells + kPrepTile - 1) / kPrepTile;
-                const int nblk = 1 + __popcll(fm);
-                A.row_ptr[c + 1] = pre_b + nblk;
-                A.dof_ptr[c + 1] = pre_d + NB;
-                A.val_ptr[pre_b + nblk] = A.tile_sum ? tv + A.tile_sum[t0].y : A.tile_off[3 * n_tiles + 1];
-            }
-        }
-    }
-    if (!A.values) return;
-
-    // groups: one per neighbour (led by its first edge) and one per boundary edge
-    const uint64_t gmask = __ballot(first || (lane < nv && o < 0));
-    const int ng = __popcll(gmask);
-    const int maxdup = __builtin_amdgcn_readfirstlane(wave_max_i(dupc));  // most edges shared with one neighbour
+    RowHead h;
+    if (!row_head(A, c, NB, h)) return;
+    const int nv = h.nv;
+    const int ng = h.ng;
 
     const CellGeo g = A.geo[c];
     RowCtx R;
@@ -725,7 +834,7 @@ __device__ __forceinline__ void row_body(const AsmArgs &A, const int c, T *wlds)
     R.bx.my = uniform(R.bx.my);
     R.bx.cx = uniform(R.bx.cx);
     R.bx.cy = uniform(R.bx.cy);
-    R.isq = uniform(1.0 / g.sqrt_box);
+    R.isq = uniform(g.isq);
     R.hx = uniform(g.hix - g.lox);
     R.hy = uniform(g.hiy - g.loy);
     R.tc = trig_centre_of(g);
@@ -736,14 +845,14 @@ __device__ __forceinline__ void row_body(const AsmArgs &A, const int c, T *wlds)
     R.tc.sy = uniform(R.tc.sy);
     R.tc.cy = uniform(R.tc.cy);
     R.tc.near = __builtin_amdgcn_readfirstlane(R.tc.near);
-    R.pen_r = uniform(g.abar * P * P / g.h);
+    R.pen_r = uniform(g.pen);
     R.lox = uniform(g.lox);
     R.loy = uniform(g.loy);
     R.hix = uniform(g.hix);
     R.hiy = uniform(g.hiy);
-    R.ihx = uniform(1.0 / (g.hix - g.lox));
-    R.ihy = uniform(1.0 / (g.hiy - g.loy));
-    R.s0 = s;
+    R.ihx = uniform(g.ihx);
+    R.ihy = uniform(g.ihy);
+    R.s0 = h.s0;
     R.red = A.reduced && A.qr_ok[c];
     R.QM = R.red ? kQrNodes : (nv - 2) * C::NQT;  // points of the element matrix
     R.QF0 = (R.QM + FG - 1) / FG * FG;            // edge groups start here
@@ -752,29 +861,21 @@ __device__ __forceinline__ void row_body(const AsmArgs &A, const int c, T *wlds)
     R.lane = lane;
     R.c = c;
     R.nv = nv;
-    R.vid = vid;
-    R.o = o;
-    R.voff = voff;
-    R.dvoff = dvoff;
-    R.maxdup = max(maxdup, 1);
+    R.vid = h.vid;
+    R.o = h.o;
+    R.voff = h.voff;
+    R.dvoff = h.dvoff;
+    R.maxdup = h.maxdup;
     R.ng = ng;
     R.xs = C::LW > 0 ? wlds : nullptr;
-    R.gmask = gmask;
-    {
-        // lane g gets the position of the g-th set bit of gmask: a forward
-        // permutation sends group leaders to lanes 0 .. ng - 1 in order and the
-        // other lanes, in order, to ng .. 63
-        const bool lead = (gmask >> lane) & 1ull;
-        const int gidx = __popcll(gmask & ((1ull << lane) - 1ull));
-        const int dst = lead ? gidx : ng + (lane - gidx);
-        R.gtab = __builtin_amdgcn_ds_permute(dst << 2, lane);
-    }
-    R.ex = ex;
-    R.ey = ey;
-    R.x0 = readlane_d(ex, 0);
-    R.y0 = readlane_d(ey, 0);
-    R.pre_v = pre_v;
-    R.pre_d = pre_d;
+    R.gmask = h.gmask;
+    R.gtab = h.gtab;
+    R.ex = h.ex;
+    R.ey = h.ey;
+    R.x0 = readlane_d(h.ex, 0);
+    R.y0 = readlane_d(h.ey, 0);
+    R.pre_v = h.pre_v;
+    R.pre_d = h.pre_d;
     row_slices<T, P, PN, MX, ADV>(A, R, std::make_integer_sequence<int, C::NSL>{});
 }
 
@@ -894,6 +995,7 @@ static size_t spill_bytes(int alt, bool adv) {
 }
 
 size_t row2d_spill_bytes(int precision, int p, bool mixed, int alt, bool adv) {
+    if (precision == 1 && !mixed && (p == 1 || p == 2)) return row2d_f32_spill_bytes(p, alt, adv);  // plain rules
 #define DGP_SP(T, PP) \
     if (p == PP) return mixed ? spill_bytes<T, PP, kMaxP, true>(alt, adv) : spill_bytes<T, PP, PP, false>(alt, adv);
     if (precision == 0) {
@@ -906,6 +1008,10 @@ size_t row2d_spill_bytes(int precision, int p, bool mixed, int alt, bool adv) {
 }
 
 bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, int alt, hipStream_t st) {
+    if (row2d_f32_applies(a, precision, p, mixed)) {
+        launch_row2d_f32(a, p, alt, st);
+        return true;
+    }
 #define DGP_ROW(T, PP)                                      \
     if (p == PP) {                                          \
         if (mixed)                                          \

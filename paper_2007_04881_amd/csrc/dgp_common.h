@@ -44,8 +44,9 @@ struct DevMesh {
     const int32_t *face_opp;  // 3D only: vertex of the left cell's tetrahedron opposite the face
 };
 
-// Per-cell geometry written by the preparation kernel, one 64-byte record per
-// cell so that a neighbour's data is two 32-byte loads from one cache line.
+// Per-cell geometry written by the preparation kernel, one 128-byte record per
+// cell (two cache lines).  The reciprocals and the penalty factor are stored
+// so that the rows reading a neighbour's record need no division.
 struct alignas(64) CellGeo {
     double lox, loy, hix, hiy;  // bounding box
     double h;                   // diameter (largest vertex distance)
@@ -53,7 +54,11 @@ struct alignas(64) CellGeo {
     double sqrt_box;            // sqrt(|bounding box|), basis normalisation
     double area;                // |kappa|
     double sx, cx, sy, cy;      // sin / cos (pi x), (pi y) at the box centre (0, 1, 0, 1 if unused)
+    double ihx, ihy;            // 1 / (hix - lox), 1 / (hiy - loy)
+    double isq;                 // 1 / sqrt_box
+    double pen;                 // abar p^2 / h at the element's own degree (diameter penalty)
 };
+static_assert(sizeof(CellGeo) == 128, "two cache lines per element");
 
 // One loop edge of an element as the assembly needs it (32 bytes).
 struct alignas(16) EdgeRec {

@@ -311,6 +311,10 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
         g.cx = tcen.cx;
         g.sy = tcen.sy;
         g.cy = tcen.cy;
+        g.ihx = 1.0 / (hix - lox);
+        g.ihy = 1.0 / (hiy - loy);
+        g.isq = 1.0 / g.sqrt_box;
+        g.pen = g.abar * double(p * p) / g.h;
         out.geo[c] = g;
     }
     if (lane == 0) {
