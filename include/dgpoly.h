@@ -313,7 +313,7 @@ typedef struct {
     float ms_features, ms_network, ms_refine; /* device time of the three stages */
     /* DGP_INIT_NETWORK: eligible elements that started from the network's rule
      * (the others from the template, whose initial residual was smaller), and
-     * elements refined again from the template after a rejected network start,
+     * elements refined again from the template after the first attempt,
      * with how many of those were accepted */
     int64_t n_start_network, n_retried, n_retry_accepted;
 } dgp_qrule_stats;
@@ -321,7 +321,8 @@ typedef struct {
 typedef struct {
     int64_t n_polygons;          /* training polygons, indices 0 .. n-1 of the seeded stream */
     uint64_t data_seed;          /* key of the polygon stream (dgp_train_polygons) */
-    uint64_t init_seed;          /* initial weights N(0, 1/fan_in), biases 0 */
+    uint64_t init_seed;          /* initial weights N(0, 1/fan_in) (output layer x 1/10), hidden biases 0,
+                                    output biases at the template rule's pre-activations */
     int32_t epochs, batch;
     float lr, beta1, beta2, eps; /* Adam */
 } dgp_train_cfg;
@@ -340,9 +341,9 @@ dgp_status dgp_mlp_load(dgp_ctx *ctx, const float *params, int64_t n_params);
  * parameters), at most max_iters damped Gauss-Newton steps (stopping at tol), the
  * acceptance flags.  With DGP_INIT_NETWORK each element starts from the
  * network's rule or the template's, whichever has the smaller moment residual,
- * and an element rejected after a network start is refined again from the
- * template (its steps count both attempts).  Synchronous; fills *out if
- * non-NULL. */
+ * for at most 3/4 of max_iters steps; an element not accepted then is refined
+ * again from the template for max_iters steps (its steps count both
+ * attempts).  Synchronous; fills *out if non-NULL. */
 dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dgp_qrule_stats *out);
 
 /* Copy the rules into caller-owned device buffers (any may be NULL):

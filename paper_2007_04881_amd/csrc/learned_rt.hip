@@ -31,7 +31,10 @@ struct DevBuf {
 };
 
 // splitmix64 (Steele, Lea and Flood, 2014) and Box-Muller normals, for the
-// initial weights N(0, 1 / fan_in); biases start at zero.
+// initial weights N(0, 1 / fan_in) (the output layer's scaled by 1/10); hidden
+// biases start at zero, the output biases at the pre-activations of the 4 x 4
+// Gauss template rule (atanh of its nodes, log of its weight products), so the
+// untrained network predicts nearly the template and training refines it.
 struct InitRng {
     uint64_t s;
     uint64_t next() {
@@ -53,8 +56,19 @@ void init_params(uint64_t seed, std::vector<float> &P) {
     const int dims[5] = {kQrIn, kQrHidden, kQrHidden, kQrHidden, kQrOut};
     const int woff[4] = {kMlpW1, kMlpW2, kMlpW3, kMlpW4};
     for (int l = 0; l < 4; ++l) {
-        const double sd = std::sqrt(1.0 / dims[l]);
+        const double sd = (l == 3 ? 0.1 : 1.0) * std::sqrt(1.0 / dims[l]);
         for (int i = 0; i < dims[l] * dims[l + 1]; ++i) P[woff[l] + i] = (float)(sd * r.normal());
+    }
+    // 4-point Gauss-Legendre on [-1, 1]: +-sqrt(3/7 -+ (2/7) sqrt(6/5)), weights (18 +- sqrt(30)) / 36
+    const double ti = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(1.2)), to = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(1.2));
+    const double t[4] = {-to, -ti, ti, to};
+    const double w[4] = {(18.0 - std::sqrt(30.0)) / 36.0, (18.0 + std::sqrt(30.0)) / 36.0, (18.0 + std::sqrt(30.0)) / 36.0,
+                         (18.0 - std::sqrt(30.0)) / 36.0};
+    float *b4 = P.data() + kMlpB4;
+    for (int k = 0; k < kQrNodes; ++k) {
+        b4[2 * k] = (float)std::atanh(t[k / 4]);
+        b4[2 * k + 1] = (float)std::atanh(t[k % 4]);
+        b4[2 * kQrNodes + k] = (float)std::log(w[k / 4] * w[k % 4]);
     }
 }
 
@@ -237,8 +251,9 @@ dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dg
     int64_t n_start_net = 0, n_retried = 0, n_retry_ok = 0;
     if (init == DGP_INIT_NETWORK) {
         // the network's rule and the template's, each element starting from the one
-        // of smaller moment residual; elements the refinement rejects after a
-        // network start are refined again from the template
+        // of smaller moment residual and refined for at most 3/4 of max_iters
+        // steps; elements that this first attempt leaves unaccepted are refined
+        // again from the template with the full max_iters (their steps add up)
         DevBuf act, tmp;
         if (!act.alloc(sizeof(float) * (size_t)N * (2 * kQrHidden + kQrOut)) ||
             !tmp.alloc((sizeof(double) * (3 * kQrNodes + 3) + sizeof(int32_t) + 4) * (size_t)N + 4 * 256))
@@ -259,8 +274,9 @@ dgp_status dgp_qrule_build(dgp_ctx *ctx, int init, int max_iters, double tol, dg
                       st);
         launch_rule_pick((int)N, res_a, res_b, ctx->qr_nodes, ctx->qr_w, nodes_t, w_t, start_tmpl, st);
         HIPCHK(ctx, hipEventRecord(ev[2], st));
+        const int first_iters = max_iters * 3 / 4 > 0 ? max_iters * 3 / 4 : max_iters;
         launch_refine((int)N, ctx->qr_mom, ctx->qr_area, ctx->qr_elig, ctx->qr_nodes, ctx->qr_w, ctx->qr_ok,
-                      ctx->qr_res, ctx->qr_iters, max_iters, tol, 1e-6, st);
+                      ctx->qr_res, ctx->qr_iters, first_iters, tol, 1e-6, st);
         launch_rule_retry_mask((int)N, ctx->qr_elig, ctx->qr_ok, start_tmpl, mask, st);
         launch_rule_init((int)N, nullptr, ctx->qr_area, nodes_t, w_t, st);
         launch_refine((int)N, ctx->qr_mom, ctx->qr_area, mask, nodes_t, w_t, acc_b, res2, it2, max_iters, tol, 1e-6, st);

@@ -515,7 +515,7 @@ __global__ void k_rule_pick(int n, const double *__restrict__ res_net, const dou
 __global__ void k_rule_retry_mask(int n, const uint8_t *__restrict__ elig, const uint8_t *__restrict__ acc,
                                   const uint8_t *__restrict__ start_tmpl, uint8_t *mask) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < n) mask[c] = elig[c] && !acc[c] && !start_tmpl[c];
+    if (c < n) mask[c] = elig[c] && !acc[c];  // either start (start_tmpl kept for the statistics)
 }
 
 // Take the retried rules that were accepted (their steps add to the first attempt's).
