@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-KERNEL_SOURCES = ["assemble_row.hip", "asm_common.h", "dgp_common.h", "rules_data.h", "wave.h"]
+KERNEL_SOURCES = ["assemble_f32.hip", "row_common.h", "asm_common.h", "dgp_common.h", "rules_data.h", "wave.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_row2d_p2_f32_voronoi16384.json")
 
 
@@ -563,7 +563,7 @@ def main():
         "kernel_ms": avg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg),
-                     "kernel": f"k_row2d<float,2,2,false,true,{alt}>", "algorithmic_bytes": abytes,
+                     "kernel": f"k_row2d_f32<2,true,{alt}>", "algorithmic_bytes": abytes,
                      "measured_copy_gbs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "valu_issue": valu_issue(cfg, avg["assemble"])},
         "upload_ms": upload_ms,

@@ -235,8 +235,8 @@ dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assem
  * degree.  Results do not depend on the configuration.  Values of the last
  * call's output buffers are rewritten (they must still be allocated).  3D
  * meshes and reduced rules have a single configuration (nothing changes).
- * Configurations whose larger occupancy makes the kernel spill more registers
- * than the default are not tried.  On a mesh of mixed degrees the tuned
+ * Configurations whose larger occupancy makes the kernel spill more than 32
+ * bytes per lane beyond the default are not tried.  On a mesh of mixed degrees the tuned
  * per-degree launches are then timed against one persistent launch over all
  * bins and the faster is kept.  choice: NULL or int32[2][5], per [FP64, FP32]:
  * entry 0 = 1 if mixed degrees take the single launch, entries 1..4 = the cfg

@@ -14,10 +14,13 @@
 //    and forms its box coordinates and coefficients in FP32; the manufactured
 //    data (a, f, boundary values) stay FP64 (sin / cos by angle addition from
 //    the box centre);
-//  * the element block and load of p = 2 go through a transposed per-wave LDS
-//    table, each lane forming one entry as a dot product over the pass's
-//    points; p = 1 keeps rank-3 register updates and a reduce-scatter (12
-//    entries); the cross blocks go through the same table;
+//  * a transposed per-wave LDS table holds, per basis function, the test
+//    terms of every point of the pass (columns 3 lane + a), then the
+//    neighbour's trial terms (cross blocks: one group at a time, lane
+//    i NB + j sums entry (i, j) over the group's columns), then the row's own
+//    trial terms and the load terms (p = 2: lane e < 42 sums entry e of the
+//    element block or load over all the pass's columns; p = 1 keeps rank-3
+//    register updates into 12 accumulators and a reduce-scatter);
 //  * sums across passes (rows of more than 64 points, edges shared twice
 //    with one neighbour) are compensated (TwoSum).
 #include "asm_common.h"
@@ -36,9 +39,9 @@ struct F32Cfg {
     static constexpr int NQT = Tri<4>::n;  // the degree-4 rule on each fan sub-triangle
     static constexpr int NG = 3;           // Gauss points per edge (max(p + 1, 3))
     static constexpr int FG = 4;           // lanes per edge group
-    static constexpr bool EL = P == 2;     // element block through the table
+    static constexpr bool EL = P == 2;     // element block and load through the table
     static constexpr int KS = 3 * 64 + 4;  // table row stride: 192 point terms + 4 (rows start 4 banks apart)
-    // rows: test terms (NB), neighbour's / own trial terms (NB), load terms (1)
+    // rows: test terms (NB), the neighbour's or the row's own trial terms (NB), load terms (1)
     static constexpr int LW = (2 * NB + 1) * KS;
 };
 
@@ -99,14 +102,13 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
     // vertex k: box coordinates and the data position
     const float v_xi = float(((h.ex - lox) - (hix - h.ex)) * ihx);
     const float v_eta = float(((h.ey - loy) - (hiy - h.ey)) * ihy);
-    const float v_px = float(h.ex - xc), v_py = float(h.ey - yc);
+    const float v_px = float(h.ex - xc), v_py = float(h.ey - yc);  // offset from the centre
+    const float v_ax = float(h.ex), v_ay = float(h.ey);              // absolute (exact for 0 and 1)
     // sub-triangle (0, k, k + 1)
     const float t_area = float(0.5 * ((h.ex - x0) * (yw - y0) - (xw - x0) * (h.ey - y0)));
     // edge k, from its lower-id end a to b
-    float e_xi = 0.0f, e_eta = 0.0f, e_dxi = 0.0f, e_deta = 0.0f;      // own box coordinates of a, b - a
-    float e_px = 0.0f, e_py = 0.0f, e_dpx = 0.0f, e_dpy = 0.0f;        // data position of a, b - a
     float e_nxi = 0.0f, e_neta = 0.0f, e_ndxi = 0.0f, e_ndeta = 0.0f;  // neighbour's box coordinates
-    float e_len = 0.0f, e_nx = 0.0f, e_ny = 0.0f, e_hs = 0.0f;         // length, normal, sigma - upwind
+    float e_len = 0.0f, e_nx = 0.0f, e_ny = 0.0f, e_hs = 0.0f;  // length (negative: a = end vertex), normal, sigma - upwind
     float e_bnx = 0.0f, e_bny = 0.0f, e_xsc = 0.0f;                    // neighbour box factor x normal, scale
     if (lane < nv) {
         const bool fwd = h.vid < vw;
@@ -117,17 +119,7 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
         const double nx = ty * dl, ny = -tx * dl;  // outward for a counter-clockwise loop
         const double bn = pr.bx * nx + pr.by * ny;
         const double up = bn < 0.0 ? bn : 0.0;
-        e_xi = float(((xa - lox) - (hix - xa)) * ihx);
-        e_eta = float(((ya - loy) - (hiy - ya)) * ihy);
-        e_dxi = float(2.0 * tx * ihx);
-        e_deta = float(2.0 * ty * ihy);
-        // data positions: offsets from the centre inside, absolute on the boundary
-        // (exact vertex coordinates there, so boundary data vanish exactly where u does)
-        e_px = float(h.o >= 0 ? xa - xc : xa);
-        e_py = float(h.o >= 0 ? ya - yc : ya);
-        e_dpx = float(tx);
-        e_dpy = float(ty);
-        e_len = float(len);
+        e_len = float(fwd ? len : -len);
         e_nx = float(nx);
         e_ny = float(ny);
         double sigma;
@@ -161,12 +153,15 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
     const int QM = (nv - 2) * NQT;             // fan sub-triangle points
     const int QF0 = (QM + FG - 1) / FG * FG;   // edge groups start here
     const int Qtot = QF0 + FG * h.ng;
-    float acc_e = 0.0f, err_e = 0.0f;          // EL: the lane's entry and its carried rounding error
+    // EL: lane e < NB (NB + 1) holds entry (e / (NB + 1), e mod (NB + 1)) of the
+    // element block (column NB: the load), with its carried rounding error
+    float acc_e = 0.0f, err_e = 0.0f;
     float acc[NB * NB + NB];                   // p = 1: element block and load, then the reduce-scatter
 #pragma unroll
     for (int e = 0; e < NB * NB + NB; ++e) acc[e] = 0.0f;
     float *U = xs, *S = xs + NB * KS, *Rr = xs + 2 * NB * KS;
     const int k0 = 3 * lane;
+    const int xi_row = lane / NB, xj_col = lane - NB * (lane / NB);  // cross-block entry of lane < NB^2
 
     for (int base = 0; base < Qtot; base += 64) {
         const int q = base + lane;
@@ -196,16 +191,16 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
             const bool epnt = edge_lane && gq < NG && fk >= 0;
             // fetch: a fan point's vertices and sub-triangle, or an edge point's edge
             const int tri = vol ? q / NQT : 0;
-            const int s1 = vol ? tri + 1 : (fk >= 0 ? fk : 0), s2 = tri + 2;
+            // s1, s2: the sub-triangle's second and third vertices, or the edge's start and end
+            const int s1 = vol ? tri + 1 : (fk >= 0 ? fk : 0);
+            const int s2 = vol ? tri + 2 : (s1 + 1 < nv ? s1 + 1 : 0);
             const float xi1 = __shfl(v_xi, s1, 64), eta1 = __shfl(v_eta, s1, 64);
             const float xi2 = __shfl(v_xi, s2, 64), eta2 = __shfl(v_eta, s2, 64);
             const float px1 = __shfl(v_px, s1, 64), py1 = __shfl(v_py, s1, 64);
             const float px2 = __shfl(v_px, s2, 64), py2 = __shfl(v_py, s2, 64);
             const float area = __shfl(t_area, s1, 64);
-            const float a_xi = __shfl(e_xi, s1, 64), a_eta = __shfl(e_eta, s1, 64);
-            const float a_dxi = __shfl(e_dxi, s1, 64), a_deta = __shfl(e_deta, s1, 64);
-            const float a_px = __shfl(e_px, s1, 64), a_py = __shfl(e_py, s1, 64);
-            const float a_dpx = __shfl(e_dpx, s1, 64), a_dpy = __shfl(e_dpy, s1, 64);
+            const float ax1 = __shfl(v_ax, s1, 64), ay1 = __shfl(v_ay, s1, 64);
+            const float ax2 = __shfl(v_ax, s2, 64), ay2 = __shfl(v_ay, s2, 64);
             const float a_nxi = __shfl(e_nxi, s1, 64), a_neta = __shfl(e_neta, s1, 64);
             const float a_ndxi = __shfl(e_ndxi, s1, 64), a_ndeta = __shfl(e_ndeta, s1, 64);
             const float a_len = __shfl(e_len, s1, 64), a_nx = __shfl(e_nx, s1, 64), a_ny = __shfl(e_ny, s1, 64);
@@ -215,15 +210,42 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
             float xi = 0.0f, eta = 0.0f, xin = 0.0f, etan = 0.0f;
             float a0 = 0.0f, a1 = 0.0f, b0 = 0.0f, b1 = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
             float x0c = 0.0f, x1c = 0.0f, r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
+            // the point: box coordinates, weight, data position (offset from the
+            // centre, or absolute on a boundary edge)
+            float W = 0.0f, tq = 0.0f, ppx = 0.0f, ppy = 0.0f;
             if (vol) {
                 const int qi = q - tri * NQT;
                 const float l1 = float(Tri<4>::l(3 * qi + 1)), l2 = float(Tri<4>::l(3 * qi + 2));
-                const float W = float(Tri<4>::w(qi)) * area;
+                W = float(Tri<4>::w(qi)) * area;
                 xi = fmaf(l1, xi1 - xi0, fmaf(l2, xi2 - xi0, xi0));
                 eta = fmaf(l1, eta1 - eta0, fmaf(l2, eta2 - eta0, eta0));
-                const float ppx = fmaf(l1, px1 - px0, fmaf(l2, px2 - px0, px0));
-                const float ppy = fmaf(l1, py1 - py0, fmaf(l2, py2 - py0, py0));
-                const PointData dd = data_near(pr, near, xc, yc, s0x, c0x, s0y, c0y, ppx, ppy, true);
+                ppx = fmaf(l1, px1 - px0, fmaf(l2, px2 - px0, px0));
+                ppy = fmaf(l1, py1 - py0, fmaf(l2, py2 - py0, py0));
+            } else if (epnt) {
+                tq = float(c_gl_t[c_gl_off[NG - 1] + gq]);
+                W = float(c_gl_w[c_gl_off[NG - 1] + gq]) * fabsf(a_len);
+                // from the lower-id end a to b (both rows place the edge's points alike)
+                const bool fwd = a_len > 0.0f;
+                const float xia = fwd ? xi1 : xi2, xib = fwd ? xi2 : xi1, etaa = fwd ? eta1 : eta2,
+                            etab = fwd ? eta2 : eta1;
+                xi = fmaf(tq, xib - xia, xia);
+                eta = fmaf(tq, etab - etaa, etaa);
+                // data position: offset from the centre inside, absolute on the boundary
+                // (exact vertex coordinates there, so boundary data vanish exactly where u does)
+                const float pxa = og >= 0 ? (fwd ? px1 : px2) : (fwd ? ax1 : ax2);
+                const float pxb = og >= 0 ? (fwd ? px2 : px1) : (fwd ? ax2 : ax1);
+                const float pya = og >= 0 ? (fwd ? py1 : py2) : (fwd ? ay1 : ay2);
+                const float pyb = og >= 0 ? (fwd ? py2 : py1) : (fwd ? ay2 : ay1);
+                ppx = fmaf(tq, pxb - pxa, pxa);
+                ppy = fmaf(tq, pyb - pya, pya);
+            }
+            // data: one evaluation shared by the element points and the interior edge points
+            PointData dd{};
+            if (vol || (epnt && og >= 0))
+                dd = data_near(pr, near, xc, yc, s0x, c0x, s0y, c0y, ppx, ppy, true);
+            else if (epnt)
+                dd = point_data(pr, double(ppx), double(ppy), false);
+            if (vol) {
                 const float Wa = W * float(dd.a);
                 a0 = Wa * cx2;
                 a1 = Wa * cy2;
@@ -234,14 +256,9 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
                 }
                 r2 = float(double(W) * dd.f);
             } else if (epnt) {
-                const float tq = float(c_gl_t[c_gl_off[NG - 1] + gq]);
-                const float w = float(c_gl_w[c_gl_off[NG - 1] + gq]) * a_len;
-                xi = fmaf(tq, a_dxi, a_xi);
-                eta = fmaf(tq, a_deta, a_eta);
-                const float ppx = fmaf(tq, a_dpx, a_px), ppy = fmaf(tq, a_dpy, a_py);
+                const float w = W;
                 const float cnx = cxf * a_nx, cny = cyf * a_ny;
                 if (og >= 0) {
-                    const PointData dd = data_near(pr, near, xc, yc, s0x, c0x, s0y, c0y, ppx, ppy, false);
                     const float ha = -0.5f * w * float(dd.a), hs = a_hs * w;
                     b0 = ha * cnx;
                     b1 = ha * cny;
@@ -252,22 +269,19 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
                     x1c = ha * a_bny;
                     xin = fmaf(tq, a_ndxi, a_nxi);
                     etan = fmaf(tq, a_ndeta, a_neta);
+                } else if (og == -1) {
+                    const float ha = -w * float(dd.a), hs = a_hs * w;
+                    b0 = ha * cnx;
+                    b1 = ha * cny;
+                    c0 = ha * cnx;
+                    c1 = ha * cny;
+                    c2 = hs;
+                    const float uu = float(dd.u);
+                    r0 = ha * uu * cnx;
+                    r1 = ha * uu * cny;
+                    r2 = hs * uu;
                 } else {
-                    const PointData dd = point_data(pr, double(ppx), double(ppy), false);
-                    if (og == -1) {
-                        const float ha = -w * float(dd.a), hs = a_hs * w;
-                        b0 = ha * cnx;
-                        b1 = ha * cny;
-                        c0 = ha * cnx;
-                        c1 = ha * cny;
-                        c2 = hs;
-                        const float uu = float(dd.u);
-                        r0 = ha * uu * cnx;
-                        r1 = ha * uu * cny;
-                        r2 = hs * uu;
-                    } else {
-                        r2 = float(double(w) * dd.a * (dd.ux * double(a_nx) + dd.uy * double(a_ny)));
-                    }
+                    r2 = float(double(w) * dd.a * (dd.ux * double(a_nx) + dd.uy * double(a_ny)));
                 }
             }
             Eval<float, P> ev;
@@ -317,23 +331,23 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
                     S[j * KS + k0 + 2] = fmaf(sx0, gj0, fmaf(sx1, gj1, sc2 * vj));
                 }
                 wave_sync();
-                // entries (group, i, j) of the pass's groups; each sums its group's 3 NG columns
-                constexpr int NBX = NB * NB;
+                // the pass's interior groups one at a time: lane i NB + j < NB^2 sums
+                // entry (i, j) over its group's 3 NG columns (16-byte aligned: 3 ql
+                // is a multiple of 12) and writes it in row-major order
                 const int gfirst = base > QF0 ? (base - QF0) / FG : 0;
                 const int glast = min(h.ng, (base + 64 - QF0) / FG);
-                const int nent = (glast - gfirst) * NBX;
-                for (int e0 = 0; e0 < nent; e0 += 64) {
-                    const int e = min(e0 + lane, nent - 1);
-                    const int gl = e / NBX, r = e - gl * NBX, i = r / NB, j = r - i * NB;
-                    const int ql = QF0 + (gfirst + gl) * FG - base;  // the group's first lane
-                    const int oge = __shfl(og, ql, 64), gvo = __shfl(gvoff, ql, 64), fke = __shfl(fk, ql, 64);
-                    const float *uu = U + i * KS + 3 * ql;
-                    const float *ss = S + j * KS + 3 * ql;
-                    float sum = 0.0f;
+                for (int gg = gfirst; gg < glast; ++gg) {
+                    const int ql = QF0 + gg * FG - base;  // the group's first lane (uniform)
+                    const int oge = __builtin_amdgcn_readlane(og, ql), fke = __builtin_amdgcn_readlane(fk, ql);
+                    if (oge < 0 || fke < 0) continue;
+                    const int gvo = __builtin_amdgcn_readlane(gvoff, ql);
+                    if (lane < NB * NB) {
+                        const float *uu = U + xi_row * KS + 3 * ql;
+                        const float *ss = S + xj_col * KS + 3 * ql;
+                        float sum = 0.0f;
 #pragma unroll
-                    for (int t = 0; t < 3 * NG; ++t) sum = fmaf(uu[t], ss[t], sum);
-                    if (e0 + lane < nent && oge >= 0 && fke >= 0) {
-                        float *dst = vals + h.pre_v + gvo + i * NB + j;
+                        for (int t = 0; t < 3 * NG; ++t) sum = fmaf(uu[t], ss[t], sum);
+                        float *dst = vals + h.pre_v + gvo + lane;
                         if (d == 0)
                             *dst = sum;
                         else
@@ -343,8 +357,11 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
                 wave_sync();  // cross entries read before the trial rows are rewritten
             }
             if constexpr (C::EL) {
-                // own trial terms and load terms; lane e < NB (NB + 1) then adds entry
-                // (i, j) = (e / (NB + 1), e mod (NB + 1)) over the pass's points
+                // element block and load of the pass: the row's own trial terms and
+                // the load terms join the test terms in the table; lane e < NB (NB + 1)
+                // then sums entry (e / (NB + 1), e mod (NB + 1)) over the columns of
+                // the pass's np points (four at a time) and adds it to its running
+                // sum with TwoSum
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
                     S[j * KS + k0] = fmaf(a0, ev.g0[j], b0 * ev.v[j]);
@@ -359,7 +376,7 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
                 if (lane < NB * (NB + 1)) {
                     const float4 *uu = reinterpret_cast<const float4 *>(U + i * KS);
                     const float4 *tt = reinterpret_cast<const float4 *>(j < NB ? S + j * KS : Rr);
-                    const int n4 = (3 * np + 3) >> 2;  // columns of the pass's points, in fours
+                    const int n4 = (3 * np + 3) >> 2;
                     float s0 = 0.0f, s1 = 0.0f;
                     int k = 0;
                     for (; k + 1 < n4; k += 2) {
@@ -374,7 +391,7 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
                     two_sum_acc(acc_e, err_e, s0);
                     two_sum_acc(acc_e, err_e, s1);
                 }
-                wave_sync();  // the table is rewritten by the next point set
+                wave_sync();
             }
         }
     }

@@ -9,6 +9,7 @@ namespace dgp {
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxP = 4;
 constexpr int kLaunchCfgs = 4;  // 2D row-kernel launch configurations (register budget x row order)
+constexpr size_t kAltSpillMax = 32;  // bytes per lane of extra spill the larger-occupancy budget may have
 constexpr int kInlineTiles = 1024;  // 2D steps on at most this many tiles launch no scan kernel          // 2D kernels are built for p = 1..4
 constexpr int kMaxFaces2D = 24;   // faces per polygon handled by the preparation kernel
 constexpr int kPrepTile = 32;     // elements per preparation work-group (a tile)

@@ -975,16 +975,16 @@ dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice) {
         for (int b = 0; b < nbins; ++b) {
             const int p = bins[b];
             const bool mixed = ctx->p_uniform <= 0;
-            // the larger-occupancy register budget is tried only if it spills no
-            // more than the default (spills cost HBM traffic the timing of one
-            // launch in isolation can hide)
+            // the larger-occupancy register budget is tried only if it spills at
+            // most kAltSpillMax bytes per lane more than the default (large
+            // spills write tens of MB per launch; a few dwords can still win)
             const size_t spill0 = row2d_spill_bytes(ctx->last_precision, p, mixed, 0, adv);
             const size_t spill1 = row2d_spill_bytes(ctx->last_precision, p, mixed, 1, adv);
             float best = 0.0f;
             int best_cfg = 0;
             for (int cfg = 0; cfg < kLaunchCfgs; ++cfg) {
                 const int alt = cfg & 1;
-                if (alt && spill1 > spill0) continue;
+                if (alt && spill1 > spill0 + kAltSpillMax) continue;
                 row_range(ctx, a, p, cfg);
                 // one warm launch, then as many timed launches as fit in the share
                 HIPCHK(ctx, hipEventRecord(ctx->ev[0], st));
