@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
 KERNEL_SOURCES = ["assemble_f32.hip", "row_common.h", "asm_common.h", "dgp_common.h", "rules_data.h", "wave.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_row2d_p2_f32_voronoi16384.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_row2d_f32_p2_voronoi16384.json")
 
 
 def kernel_source_digest():
