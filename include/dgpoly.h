@@ -176,9 +176,12 @@ dgp_status dgp_pattern_copy(dgp_ctx *ctx, int64_t *row_ptr, int32_t *col_idx, in
  * rule_mode DGP_RULE_REDUCED integrates the volume matrix of every element
  * whose reduced rule was accepted by dgp_qrule_build with that rule, and the
  * rest as DGP_RULE_PLAIN; the load vector and the faces always use the plain
- * rules.  It needs constant coefficients (a1 = 0) and p <= 3, so that every
- * volume integrand has degree <= 6 (DGP_EINVAL / DGP_EUNSUPPORTED otherwise),
- * and a prior dgp_qrule_build (DGP_ESTATE). */
+ * rules.  It needs p <= 3 (DGP_EUNSUPPORTED otherwise), so that with constant
+ * coefficients every volume integrand has degree <= 6 and both rules give it
+ * to rounding; with a variable a (a1 != 0) neither rule is exact and the two
+ * differ by their quadrature errors, O(h^(7 - 2 (p - 1))) relative to the
+ * block as the mesh is refined (a's Taylor terms of degree <= 6 - 2 (p - 1)
+ * are integrated exactly).  Needs a prior dgp_qrule_build (DGP_ESTATE). */
 dgp_status dgp_assemble(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rule_mode, void *vals, void *rhs);
 
 /* The whole path on the device: pattern (recomputed into the context's

@@ -691,8 +691,6 @@ static dgp_status check_assemble_args(dgp_ctx *ctx, const dgp_problem *prob, int
     }
     if (rule_mode == DGP_RULE_REDUCED) {
         if (!ctx->has_qrule) return fail(ctx, DGP_ESTATE, "reduced rules requested before dgp_qrule_build");
-        if (prob->a1 != 0.0)
-            return fail(ctx, DGP_EINVAL, "reduced rules integrate polynomials of degree <= 6: a must be constant");
         if (ctx->p_max > 3) return fail(ctx, DGP_EUNSUPPORTED, "reduced rules need p <= 3");
     }
     return DGP_OK;
