@@ -113,6 +113,10 @@ def test_pure_advection(precision):
     m = m.with_degrees(np.random.default_rng(10).integers(1, 5, m.n_cells))
     _case(m, dict(a0=0.0, a1=0.0, b=(1.0, -0.4, 0.0), c=0.5, c_sigma=10.0, u="sin"), precision)
     _case(m, dict(POLY, a0=0.0), precision)
+    # one degree (the FP32 one-degree row kernel for p <= 2)
+    for p in (1, 2):
+        u = voronoi_mesh(500, 89, lloyd=1, p=p)
+        _case(u, dict(a0=0.0, a1=0.0, b=(1.0, -0.4, 0.0), c=0.5, c_sigma=10.0, u="sin"), precision)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -131,16 +135,19 @@ def test_covering_penalty(precision):
     _case(g, dict(DAR, penalty="covering"), precision, full_path=True)
 
 
-def test_cartesian_and_neumann():
-    m = cartesian_mesh(7, 5, p=2, x0=0.1, x1=1.3, y0=-0.2, y1=0.9)
-    _case(m, DAR, 0)
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cartesian_and_neumann(p, precision):
+    m = cartesian_mesh(7, 5, p=p, x0=0.1, x1=1.3, y0=-0.2, y1=0.9)
+    _case(m, DAR, precision)
     # turn the faces on the left side into Neumann faces
-    m2 = cartesian_mesh(7, 5, p=2)
+    m2 = cartesian_mesh(7, 5, p=p)
     xl = np.where(m2.x == 0.0)[0]
     fv = m2.face_vtx.reshape(-1, 2)
     left = np.isin(fv[:, 0], xl) & np.isin(fv[:, 1], xl)
     m2.face_bc[left] = 2
-    _case(m2, DAR, 0)
+    _case(m2, DAR, precision)
+    _case(m2, POLY, precision)
 
 
 @pytest.mark.parametrize("p", [1, 2, "mixed"])
