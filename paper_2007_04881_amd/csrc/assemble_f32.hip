@@ -69,6 +69,17 @@ __device__ __forceinline__ void two_sum_acc(float &s, float &e, float b) {
     s = t;
 }
 
+// a * d/dxi phi_j + b and a * d/deta phi_j + b, with b alone when phi_j is
+// constant in that direction (j is an unrolled index: the test folds away)
+template <int P>
+__device__ __forceinline__ float fma_gx(const Eval<float, P> &ev, int j, float a, float b) {
+    return exp_a(j) > 0 ? fmaf(a, ev.g0[j], b) : b;
+}
+template <int P>
+__device__ __forceinline__ float fma_gy(const Eval<float, P> &ev, int j, float a, float b) {
+    return exp_b(j) > 0 ? fmaf(a, ev.g1[j], b) : b;
+}
+
 // Element row c (degree P, all neighbours of degree P) in one wave.
 template <int P, bool ADV>
 __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs) {
@@ -161,7 +172,6 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
     for (int e = 0; e < NB * NB + NB; ++e) acc[e] = 0.0f;
     float *U = xs, *S = xs + NB * KS, *Rr = xs + 2 * NB * KS;
     const int k0 = 3 * lane;
-    const int xi_row = lane / NB, xj_col = lane - NB * (lane / NB);  // cross-block entry of lane < NB^2
 
     for (int base = 0; base < Qtot; base += 64) {
         const int q = base + lane;
@@ -290,22 +300,22 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
             if constexpr (!C::EL) {
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
-                    const float t0 = fmaf(a0, ev.g0[j], b0 * ev.v[j]);
-                    const float t1 = fmaf(a1, ev.g1[j], b1 * ev.v[j]);
-                    const float t2 = fmaf(c0, ev.g0[j], fmaf(c1, ev.g1[j], c2 * ev.v[j]));
+                    const float t0 = fma_gx(ev, j, a0, b0 * ev.v[j]);
+                    const float t1 = fma_gy(ev, j, a1, b1 * ev.v[j]);
+                    const float t2 = fma_gx(ev, j, c0, fma_gy(ev, j, c1, c2 * ev.v[j]));
 #pragma unroll
                     for (int i = 0; i < NB; ++i)
-                        acc[i * NB + j] = fmaf(ev.g0[i], t0, fmaf(ev.g1[i], t1, fmaf(ev.v[i], t2, acc[i * NB + j])));
+                        acc[i * NB + j] = fma_gx(ev, i, t0, fma_gy(ev, i, t1, fmaf(ev.v[i], t2, acc[i * NB + j])));
                 }
 #pragma unroll
                 for (int i = 0; i < NB; ++i)
-                    acc[NB * NB + i] = fmaf(ev.g0[i], r0, fmaf(ev.g1[i], r1, fmaf(ev.v[i], r2, acc[NB * NB + i])));
+                    acc[NB * NB + i] = fma_gx(ev, i, r0, fma_gy(ev, i, r1, fmaf(ev.v[i], r2, acc[NB * NB + i])));
             }
             // ---- the table: normalised test terms of every lane's point
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
-                U[i * KS + k0] = ev.g0[i] * float(kNorm[i]);
-                U[i * KS + k0 + 1] = ev.g1[i] * float(kNorm[i]);
+                U[i * KS + k0] = fma_gx(ev, i, float(kNorm[i]), 0.0f);
+                U[i * KS + k0 + 1] = fma_gy(ev, i, float(kNorm[i]), 0.0f);
                 U[i * KS + k0 + 2] = ev.v[i] * float(kNorm[i]);
             }
             if (pass_has_edges) {
@@ -324,30 +334,43 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
                             sc2 = -c2 * a_xsc;
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
+                    // (a gradient component of a function constant in that direction is left out)
                     const float vj = Lx[exp_a(j)] * Ly[exp_b(j)];
-                    const float gj0 = dLx[exp_a(j)] * Ly[exp_b(j)], gj1 = Lx[exp_a(j)] * dLy[exp_b(j)];
+                    float t2 = sc2 * vj;
+                    if (exp_a(j) > 0) t2 = fmaf(sx0, dLx[exp_a(j)] * Ly[exp_b(j)], t2);
+                    if (exp_b(j) > 0) t2 = fmaf(sx1, Lx[exp_a(j)] * dLy[exp_b(j)], t2);
                     S[j * KS + k0] = sb0 * vj;
                     S[j * KS + k0 + 1] = sb1 * vj;
-                    S[j * KS + k0 + 2] = fmaf(sx0, gj0, fmaf(sx1, gj1, sc2 * vj));
+                    S[j * KS + k0 + 2] = t2;
                 }
                 wave_sync();
-                // the pass's interior groups one at a time: lane i NB + j < NB^2 sums
-                // entry (i, j) over its group's 3 NG columns (16-byte aligned: 3 ql
-                // is a multiple of 12) and writes it in row-major order
+                // every interior group of the pass at once: entry e of the pass's
+                // groups (NB^2 per group, row-major inside it) goes to lane e mod 64
+                // of round e / 64; the lane sums u(i) s(j) over its group's 3 NG
+                // columns (16-byte aligned: 3 ql is a multiple of 12) and writes it
                 const int gfirst = base > QF0 ? (base - QF0) / FG : 0;
                 const int glast = min(h.ng, (base + 64 - QF0) / FG);
-                for (int gg = gfirst; gg < glast; ++gg) {
-                    const int ql = QF0 + gg * FG - base;  // the group's first lane (uniform)
-                    const int oge = __builtin_amdgcn_readlane(og, ql), fke = __builtin_amdgcn_readlane(fk, ql);
-                    if (oge < 0 || fke < 0) continue;
-                    const int gvo = __builtin_amdgcn_readlane(gvoff, ql);
-                    if (lane < NB * NB) {
-                        const float *uu = U + xi_row * KS + 3 * ql;
-                        const float *ss = S + xj_col * KS + 3 * ql;
-                        float sum = 0.0f;
-#pragma unroll
-                        for (int t = 0; t < 3 * NG; ++t) sum = fmaf(uu[t], ss[t], sum);
-                        float *dst = vals + h.pre_v + gvo + lane;
+                const int nent = (glast - gfirst) * (NB * NB);
+                // the lane's group: its block's value offset, or -1 (boundary edge,
+                // or no d-th edge towards this neighbour)
+                const int gv = edge_lane && og >= 0 && fk >= 0 ? gvoff : -1;
+                for (int e0 = 0; e0 < nent; e0 += 64) {
+                    const int e = e0 + lane;
+                    const int gl = e / (NB * NB);
+                    const int ij = e - gl * (NB * NB);
+                    const int ql = min(QF0 + (gfirst + gl) * FG - base, 63);  // the group's first lane
+                    const int gvq = __shfl(gv, ql, 64);
+                    if (e < nent && gvq >= 0) {
+                        const int i = ij / NB, j = ij - NB * (ij / NB);
+                        const float *uu = U + i * KS + 3 * ql;
+                        const float *ss = S + j * KS + 3 * ql;
+                        static_assert(3 * NG == 9 && KS % 4 == 0, "two float4 and one float per row");
+                        const float4 ua = reinterpret_cast<const float4 *>(uu)[0], ub = reinterpret_cast<const float4 *>(uu)[1];
+                        const float4 sa = reinterpret_cast<const float4 *>(ss)[0], sb = reinterpret_cast<const float4 *>(ss)[1];
+                        float sum = uu[8] * ss[8];
+                        sum = fmaf(ua.x, sa.x, fmaf(ua.y, sa.y, fmaf(ua.z, sa.z, fmaf(ua.w, sa.w, sum))));
+                        sum = fmaf(ub.x, sb.x, fmaf(ub.y, sb.y, fmaf(ub.z, sb.z, fmaf(ub.w, sb.w, sum))));
+                        float *dst = vals + h.pre_v + gvq + ij;
                         if (d == 0)
                             *dst = sum;
                         else
@@ -364,9 +387,9 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
                 // sum with TwoSum
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
-                    S[j * KS + k0] = fmaf(a0, ev.g0[j], b0 * ev.v[j]);
-                    S[j * KS + k0 + 1] = fmaf(a1, ev.g1[j], b1 * ev.v[j]);
-                    S[j * KS + k0 + 2] = fmaf(c0, ev.g0[j], fmaf(c1, ev.g1[j], c2 * ev.v[j]));
+                    S[j * KS + k0] = fma_gx(ev, j, a0, b0 * ev.v[j]);
+                    S[j * KS + k0 + 1] = fma_gy(ev, j, a1, b1 * ev.v[j]);
+                    S[j * KS + k0 + 2] = fma_gx(ev, j, c0, fma_gy(ev, j, c1, c2 * ev.v[j]));
                 }
                 Rr[k0] = r0;
                 Rr[k0 + 1] = r1;
