@@ -32,6 +32,8 @@ namespace dgp {
 
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <int P>
 struct F32Cfg {
     static_assert(P == 1 || P == 2, "FP32 rows of degree 1 or 2");
@@ -381,10 +383,8 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
             }
             if constexpr (C::EL) {
                 // element block and load of the pass: the row's own trial terms and
-                // the load terms join the test terms in the table; lane e < NB (NB + 1)
-                // then sums entry (e / (NB + 1), e mod (NB + 1)) over the columns of
-                // the pass's np points (four at a time) and adds it to its running
-                // sum with TwoSum
+                // the load terms join the test terms in the table (the load terms as
+                // trial row NB), and the matrix cores form the NB x (NB + 1) product
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
                     S[j * KS + k0] = fma_gx(ev, j, a0, b0 * ev.v[j]);
@@ -395,24 +395,51 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
                 Rr[k0 + 1] = r1;
                 Rr[k0 + 2] = r2;
                 wave_sync();
-                const int i = lane / (NB + 1), j = lane - (NB + 1) * i;
+                // 4 x 4 x 1 matrix products in 16 blocks: block b takes the pass's
+                // points b, b + 16, ...; its lane 4 b + r supplies test row r (rows
+                // 0-3) and 4 + r (rows 4, 5) and trial row r (columns 0-3) and 4 + r
+                // (columns 4, 5 and the load), one term a of the rank-3 form per
+                // product.  Rows past the block (r >= 2 of the second test slice,
+                // r = 3 of the second trial slice) read a valid table row: they only
+                // feed output entries that are never read.
+                const int bk = lane >> 2, rr = lane & 3;
+                const float *ua = U + rr * KS, *ub = U + (4 + min(rr, 1)) * KS;
+                const float *ta = S + rr * KS, *tb = S + (4 + min(rr, 2)) * KS;  // S row 6 is the load row
+                f32x4 m00 = {0.0f, 0.0f, 0.0f, 0.0f}, m01 = m00, m10 = m00, m11 = m00;
+                const int nr = (np + 15) >> 4;
+                for (int k = 0; k < nr; ++k) {
+                    const int col = 3 * (16 * k + bk);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float xa = ua[col + a], xb = ub[col + a], ya = ta[col + a], yb = tb[col + a];
+                        m00 = __builtin_amdgcn_mfma_f32_4x4x1f32(xa, ya, m00, 0, 0, 0);
+                        m01 = __builtin_amdgcn_mfma_f32_4x4x1f32(xa, yb, m01, 0, 0, 0);
+                        m10 = __builtin_amdgcn_mfma_f32_4x4x1f32(xb, ya, m10, 0, 0, 0);
+                        m11 = __builtin_amdgcn_mfma_f32_4x4x1f32(xb, yb, m11, 0, 0, 0);
+                    }
+                }
+                wave_sync();  // every table read done before the partial sums overwrite the test rows
+                // the 16 blocks' partial sums to LDS, entry-major (entry (4 s + x, 4 t + y)
+                // of slice pair (s, t) at red[((2 s + t) 16 + 4 x + y) 16 + block]), then
+                // lane e < NB (NB + 1) adds up its entry's 16 and carries it into its
+                // running sum with TwoSum
+                float *red = U;
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    red[((0 * 16) + 4 * x + rr) * 16 + bk] = m00[x];
+                    red[((1 * 16) + 4 * x + rr) * 16 + bk] = m01[x];
+                    red[((2 * 16) + 4 * x + rr) * 16 + bk] = m10[x];
+                    red[((3 * 16) + 4 * x + rr) * 16 + bk] = m11[x];
+                }
+                wave_sync();
                 if (lane < NB * (NB + 1)) {
-                    const float4 *uu = reinterpret_cast<const float4 *>(U + i * KS);
-                    const float4 *tt = reinterpret_cast<const float4 *>(j < NB ? S + j * KS : Rr);
-                    const int n4 = (3 * np + 3) >> 2;
-                    float s0 = 0.0f, s1 = 0.0f;
-                    int k = 0;
-                    for (; k + 1 < n4; k += 2) {
-                        const float4 ua = uu[k], ta = tt[k], ub = uu[k + 1], tb = tt[k + 1];
-                        s0 = fmaf(ua.x, ta.x, fmaf(ua.y, ta.y, fmaf(ua.z, ta.z, fmaf(ua.w, ta.w, s0))));
-                        s1 = fmaf(ub.x, tb.x, fmaf(ub.y, tb.y, fmaf(ub.z, tb.z, fmaf(ub.w, tb.w, s1))));
-                    }
-                    if (k < n4) {
-                        const float4 ua = uu[k], ta = tt[k];
-                        s0 = fmaf(ua.x, ta.x, fmaf(ua.y, ta.y, fmaf(ua.z, ta.z, fmaf(ua.w, ta.w, s0))));
-                    }
-                    two_sum_acc(acc_e, err_e, s0);
-                    two_sum_acc(acc_e, err_e, s1);
+                    const int ie = lane / (NB + 1), je = lane - (NB + 1) * ie;
+                    const int sp = 2 * (ie >> 2) + (je >> 2);
+                    const float4 *pp = reinterpret_cast<const float4 *>(red + (sp * 16 + 4 * (ie & 3) + (je & 3)) * 16);
+                    const float4 q0 = pp[0], q1 = pp[1], q2 = pp[2], q3 = pp[3];
+                    const float sum = ((q0.x + q0.y) + (q0.z + q0.w)) + ((q1.x + q1.y) + (q1.z + q1.w)) +
+                                      (((q2.x + q2.y) + (q2.z + q2.w)) + ((q3.x + q3.y) + (q3.z + q3.w)));
+                    two_sum_acc(acc_e, err_e, sum);
                 }
                 wave_sync();
             }
