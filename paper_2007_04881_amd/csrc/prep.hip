@@ -85,6 +85,50 @@ __device__ double max_a_points(const DevProblem &pr, const TrigCentre &tc, const
     return amax;
 }
 
+// The element's loop edges towards neighbours (nb >= 0) in the first NS slots of
+// its G lanes: whether each is the first edge towards its neighbour (bit q of
+// firstm) and how many of the loop's edges face that neighbour (dup)
+template <int NS>
+__device__ __forceinline__ void edge_dups(const int *nb, int lane, int base, int &firstm, int *dup) {
+#pragma unroll
+    for (int q2 = 0; q2 < NS; ++q2)
+        for (int l2 = 0; l2 < G; ++l2) {
+            const int v = __shfl(nb[q2], base + l2, 64);
+            const int j = l2 + G * q2;
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (v == nb[q]) {
+                    if (j < lane + G * q) firstm &= ~(1 << q);
+                    dup[q] += 1;
+                }
+        }
+}
+
+// Column ranks and value offsets of the blocks of the first NS slots' edges
+// (key: the neighbour's block size at its first edge, else 0), and of the
+// diagonal block (column c)
+template <int NS>
+__device__ __forceinline__ void edge_ranks(const int *nb, const int *key, int c, int nbc, int base, int *rank,
+                                           int *voff, int &drank, int &dvoff) {
+#pragma unroll
+    for (int q2 = 0; q2 < NS; ++q2)
+        for (int l2 = 0; l2 < G; ++l2) {
+            const int v = __shfl(nb[q2], base + l2, 64);
+            const int vs = __shfl(key[q2], base + l2, 64);
+            const int one = vs > 0 ? 1 : 0, w = nbc * vs;  // both 0 unless edge j is a first edge
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (v < nb[q]) {
+                    rank[q] += one;
+                    voff[q] += w;
+                }
+            if (v < c) {
+                drank += one;
+                dvoff += w;
+            }
+        }
+}
+
 }  // namespace
 
 // p_uniform > 0: every cell has that degree (no neighbour degree is read)
@@ -198,31 +242,25 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
     // a neighbour counts once, at its first face
     // loop slots used by some element of this wave (most polygons fill one)
     const int nvmax = __builtin_amdgcn_readfirstlane(wave_max_i(nv));
-    bool first[SLOTS];
+    const int nslot = (nvmax + G - 1) / G;
+    int firstm = 0;  // bit q: slot q's edge is the first towards its neighbour
     int dup[SLOTS];  // edges of the loop towards the same neighbour
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
-        first[q] = nb[q] >= 0;
+        if (nb[q] >= 0) firstm |= 1 << q;
         dup[q] = 0;
     }
-#pragma unroll
-    for (int q2 = 0; q2 < SLOTS; ++q2) {
-        if (G * q2 >= nvmax) break;
-        for (int l2 = 0; l2 < G; ++l2) {
-            const int v = __shfl(nb[q2], base + l2, 64);
-            const int j = l2 + G * q2;
-#pragma unroll
-            for (int q = 0; q < SLOTS; ++q)
-                if (v == nb[q]) {
-                    if (j < lane + G * q) first[q] = false;
-                    dup[q] += 1;
-                }
-        }
-    }
+    static_assert(SLOTS == 3, "one instantiation per slot count");
+    if (nslot <= 1)
+        edge_dups<1>(nb, lane, base, firstm, dup);
+    else if (nslot == 2)
+        edge_dups<2>(nb, lane, base, firstm, dup);
+    else
+        edge_dups<3>(nb, lane, base, firstm, dup);
     int cnt = 0, szsum = 0;
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q)
-        if (first[q]) {
+        if ((firstm >> q) & 1) {
             cnt += 1;
             szsum += nbsz[q];
         }
@@ -235,33 +273,20 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
 
     // block ranks and value offsets (columns ascending; the diagonal block is column c)
     int rank[SLOTS], voff[SLOTS];
+    int key[SLOTS];  // a neighbour's block size at its first edge, else 0
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
         rank[q] = nb[q] > c ? 1 : 0;
         voff[q] = nb[q] > c ? nbc * nbc : 0;
+        key[q] = ((firstm >> q) & 1) ? nbsz[q] : 0;
     }
     int drank = 0, dvoff = 0;
-#pragma unroll
-    for (int q2 = 0; q2 < SLOTS; ++q2) {
-        if (G * q2 >= nvmax) break;
-        for (int l2 = 0; l2 < G; ++l2) {
-            const int v = __shfl(nb[q2], base + l2, 64);
-            const int vf = __shfl((int)first[q2], base + l2, 64);
-            const int vs = __shfl(nbsz[q2], base + l2, 64);
-            if (vf) {
-#pragma unroll
-                for (int q = 0; q < SLOTS; ++q)
-                    if (v < nb[q]) {
-                        rank[q] += 1;
-                        voff[q] += nbc * vs;
-                    }
-                if (v < c) {
-                    drank += 1;
-                    dvoff += nbc * vs;
-                }
-            }
-        }
-    }
+    if (nslot <= 1)
+        edge_ranks<1>(nb, key, c, nbc, base, rank, voff, drank, dvoff);
+    else if (nslot == 2)
+        edge_ranks<2>(nb, key, c, nbc, base, rank, voff, drank, dvoff);
+    else
+        edge_ranks<3>(nb, key, c, nbc, base, rank, voff, drank, dvoff);
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
         const int f = lane + G * q;
@@ -271,7 +296,7 @@ __global__ void __launch_bounds__(WG) k_prep(DevMesh m, DevProblem pr, PrepOut o
             r.y = yq[q];
             r.vid = vq[q];
             r.o = code[q];
-            r.rank = nb[q] >= 0 ? (rank[q] | (dup[q] << kEdgeDupShift) | (first[q] ? kEdgeFirst : 0)) : 0;
+            r.rank = nb[q] >= 0 ? (rank[q] | (dup[q] << kEdgeDupShift) | (((firstm >> q) & 1) ? kEdgeFirst : 0)) : 0;
             r.voff = nb[q] >= 0 ? voff[q] : 0;
             out.erec[s + f] = r;
         }
