@@ -101,7 +101,9 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
     const double lox = g.lox, loy = g.loy, hix = g.hix, hiy = g.hiy, ihx = g.ihx, ihy = g.ihy;
     const double xc = 0.5 * (lox + hix), yc = 0.5 * (loy + hiy);
     const double hxd = hix - lox, hyd = hiy - loy;
-    const bool near = kPi * 0.5 * sqrt(hxd * hxd + hyd * hyd) <= kNearT;  // data by angle addition from the centre
+    // data by angle addition from the centre when pi |half diagonal| <= kNearT
+    constexpr double kNearD2 = (2.0 * kNearT / kPi) * (2.0 * kNearT / kPi);
+    const bool near = hxd * hxd + hyd * hyd <= kNearD2;
     const float cxf = float(2.0 * ihx), cyf = float(2.0 * ihy);          // box factors 2 / h
     const float cx2 = float(4.0 * ihx * ihx), cy2 = float(4.0 * ihy * ihy);
     const double s0x = g.sx, c0x = g.cx, s0y = g.sy, c0y = g.cy;
@@ -127,14 +129,21 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
         const bool fwd = h.vid < vw;
         const double xa = fwd ? h.ex : xw, ya = fwd ? h.ey : yw;
         const double tx = (fwd ? xw : h.ex) - xa, ty = (fwd ? yw : h.ey) - ya;
-        const double len = sqrt(tx * tx + ty * ty);
-        const double dl = (fwd ? 1.0 : -1.0) / len;
-        const double nx = ty * dl, ny = -tx * dl;  // outward for a counter-clockwise loop
-        const double bn = pr.bx * nx + pr.by * ny;
-        const double up = bn < 0.0 ? bn : 0.0;
-        e_len = float(fwd ? len : -len);
-        e_nx = float(nx);
-        e_ny = float(ny);
+        // length and normal in FP32 from the FP64 edge vector rounded once
+        // (reciprocal square root: about one ulp, as the rounding of the values)
+        const float txf = float(tx), tyf = float(ty);
+        const float l2 = fmaf(txf, txf, tyf * tyf);
+        const float il = __builtin_amdgcn_rsqf(l2);
+        const float len = l2 * il;
+        const float dl = fwd ? il : -il;
+        const float nx = tyf * dl, ny = -txf * dl;  // outward for a counter-clockwise loop
+        // b.n with its cancellation in FP64 (an edge nearly along b has a tiny
+        // upwind weight, which must keep its relative accuracy)
+        const float bn = float(pr.bx * ty - pr.by * tx) * dl;
+        const float up = bn < 0.0f ? bn : 0.0f;
+        e_len = fwd ? len : -len;
+        e_nx = nx;
+        e_ny = ny;
         double sigma;
         if (h.o >= 0) {
             const CellGeo go = A.geo[h.o];
@@ -142,19 +151,19 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
             e_neta = float(((ya - go.loy) - (go.hiy - ya)) * go.ihy);
             e_ndxi = float(2.0 * tx * go.ihx);
             e_ndeta = float(2.0 * ty * go.ihy);
-            e_bnx = float(2.0 * go.ihx * nx);
-            e_bny = float(2.0 * go.ihy * ny);
+            e_bnx = float(2.0 * go.ihx) * nx;
+            e_bny = float(2.0 * go.ihy) * ny;
             e_xsc = float(isq * go.isq);
             sigma = pr.c_sigma * (g.pen > go.pen ? g.pen : go.pen);
             if (pr.penalty == 1) {
                 const int F = m.cell_face[h.s0 + lane];
-                sigma = pr.c_sigma * len * fmax(A.pen_face[2 * F], A.pen_face[2 * F + 1]);
+                sigma = pr.c_sigma * double(len) * fmax(A.pen_face[2 * F], A.pen_face[2 * F + 1]);
             }
         } else {
             sigma = pr.c_sigma * g.pen;
-            if (pr.penalty == 1) sigma = pr.c_sigma * len * A.pen_face[2 * m.cell_face[h.s0 + lane]];
+            if (pr.penalty == 1) sigma = pr.c_sigma * double(len) * A.pen_face[2 * m.cell_face[h.s0 + lane]];
         }
-        e_hs = float(sigma - up);
+        e_hs = float(sigma - double(up));
     }
     // vertex 0 (the fan apex), uniform
     const float xi0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v_xi)));
