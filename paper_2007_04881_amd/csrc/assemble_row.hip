@@ -88,6 +88,11 @@ struct RowCfg {
     // FP64 the staged trial terms cost those kernels a wave per SIMD: slower)
     static constexpr bool CM = !XL && (P >= 3 || (PN > P && sizeof(T) == 4));
     static constexpr int CMW = 2 * 3 * FG * 16;  // its table per wave (T elements)
+    // VU: edge groups of 4 or 8 lanes (units of 4), by the Gauss points each
+    // edge needs (a row of degree < 4 needs 8 only towards degree-4
+    // neighbours): 8-lane groups first, each starting on an 8-lane boundary,
+    // so no group straddles a pass of 64 lanes
+    static constexpr bool VU = CM && FG == 8 && P < 4 && PN > P;
     // one LDS region per wave serves every table (their phases are separated by wave barriers)
     static constexpr int LW0 = EL ? (2 * NB + 1) * KS : XL ? 64 * XW : 0, LW1 = MF ? MFW : 0, LW2 = CM ? CMW : 0;
     static constexpr int LW = LW0 > LW1 ? (LW0 > LW2 ? LW0 : LW2) : (LW1 > LW2 ? LW1 : LW2);
@@ -169,6 +174,7 @@ struct RowCtx {
     int lane, c, nv, vid, o, voff, dvoff, maxdup, QM, QF0, Qtot, QR;
     int gtab;  // lane g < number of groups: loop index of the g-th group's leading edge
     int ng;    // number of edge groups
+    int n2;    // VU kernels: groups 0 .. n2 - 1 have 8 lanes, the others 4
     void *xs;  // the wave's cross-block table in LDS (XL kernels)
     bool red;
     uint64_t gmask;
@@ -419,14 +425,25 @@ __device__ __forceinline__ void cross_mf(const AsmArgs &A, const RowCtx &R, cons
             sv[2][j] = fmat(sx0, gj0, fmat(sx1, gj1, sc2 * vj));
         }
     }
-    const int gfirst = base > R.QF0 ? (base - R.QF0) / FG : 0;
-    const int glast = min(R.ng, (base + 64 - R.QF0) / FG);
+    int gfirst, glast;
+    if constexpr (C::VU) {
+        // groups whose units lie in this pass's units [ub, ue)
+        const int ub = max(base - R.QF0, 0) >> 2, ue = max(base + 64 - R.QF0, 0) >> 2;
+        const int n2 = R.n2;
+        gfirst = min(ub <= 2 * n2 ? (ub + 1) >> 1 : ub - n2, R.ng);
+        glast = min(ue <= 2 * n2 ? (ue + 1) >> 1 : ue - n2, R.ng);
+    } else {
+        gfirst = base > R.QF0 ? (base - R.QF0) / FG : 0;
+        glast = min(R.ng, (base + 64 - R.QF0) / FG);
+    }
     T *__restrict__ vals = static_cast<T *>(A.vals);
     for (int g = gfirst; g < glast; ++g) {
-        const int ql = R.QF0 + g * FG - base;  // the group's first lane (uniform)
+        // the group's first lane and its lanes (uniform)
+        const int ql = R.QF0 + (C::VU ? (g < R.n2 ? 8 * g : 4 * (R.n2 + g)) : g * FG) - base;
+        const int fgl = C::VU ? (g < R.n2 ? 8 : 4) : FG;
         const int oge = __builtin_amdgcn_readlane(og, ql), fke = __builtin_amdgcn_readlane(fk, ql);
         if (oge < 0 || fke < 0) continue;
-        if (lane >= ql && lane < ql + FG) {
+        if (lane >= ql && lane < ql + fgl) {
             const int k0 = 3 * (lane - ql);
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
@@ -442,8 +459,10 @@ __device__ __forceinline__ void cross_mf(const AsmArgs &A, const RowCtx &R, cons
         wave_sync();
         MfAcc<T> acc = {T(0), T(0), T(0), T(0)};
         const int r4 = lane >> 4, c = lane & 15;
+        const int ks = 3 * fgl / 4;  // matrix steps over the group's 3 fgl table rows
 #pragma unroll
-        for (int s = 0; s < KR / 4; ++s) acc = mfma16(U[(4 * s + r4) * 16 + c], S[(4 * s + r4) * 16 + c], acc);
+        for (int s = 0; s < KR / 4; ++s)
+            if (s < ks) acc = mfma16(U[(4 * s + r4) * 16 + c], S[(4 * s + r4) * 16 + c], acc);
         wave_sync();  // the next group rewrites the table
         const int nbog = __builtin_amdgcn_readlane(nbo, ql), gvo = __builtin_amdgcn_readlane(gvoff, ql);
 #pragma unroll
@@ -485,8 +504,15 @@ __device__ __forceinline__ void row_slice(const AsmArgs &A, const RowCtx &R) {
     for (int base = 0; base < Qtot; base += 64) {
         const int q = base + lane;
         const bool edge_lane = q >= QF0 && q < Qtot;
-        const int gi = edge_lane ? (q - QF0) / FG : 0;
-        const int gq = edge_lane ? (q - QF0) - gi * FG : 0;
+        int gi, gq;  // the lane's edge group and its point in the group
+        if constexpr (C::VU) {
+            const int u = (q - QF0) >> 2;  // 4-lane unit (QF0 is a multiple of 8)
+            gi = edge_lane ? (u < 2 * R.n2 ? u >> 1 : u - R.n2) : 0;
+            gq = edge_lane ? (u < 2 * R.n2 ? (u & 1) << 2 : 0) + (q & 3) : 0;
+        } else {
+            gi = edge_lane ? (q - QF0) / FG : 0;
+            gq = edge_lane ? (q - QF0) - gi * FG : 0;
+        }
         // leader edge of the lane's group
         const int fl = __shfl(R.gtab, gi, 64);
         const int og = __shfl(o, fl, 64);
@@ -857,6 +883,23 @@ __device__ __forceinline__ void row_body(const AsmArgs &A, const int c, T *wlds)
     R.QM = R.red ? kQrNodes : (nv - 2) * C::NQT;  // points of the element matrix
     R.QF0 = (R.QM + FG - 1) / FG * FG;            // edge groups start here
     R.Qtot = R.QF0 + FG * ng;
+    R.n2 = 0;
+    R.gtab = h.gtab;
+    if constexpr (C::VU) {
+        // the groups that need 8 lanes (more than 4 Gauss points: a degree-4
+        // neighbour) first, each in loop order; the others after them
+        const bool lead = (h.gmask >> lane) & 1ull;
+        const int po = (lead && h.o >= 0) ? (int)A.m.cell_p[h.o] : P;
+        const bool wide = lead && (P > po ? P : po) + 1 > 4;
+        const uint64_t m2 = __ballot(wide), m1 = h.gmask & ~m2;
+        const int n2 = __popcll(m2);
+        const uint64_t below = (1ull << lane) - 1ull;
+        const int gidx = wide ? __popcll(m2 & below) : n2 + __popcll(m1 & below);
+        const int dst = lead ? gidx : ng + (lane - __popcll(h.gmask & below));
+        R.gtab = __builtin_amdgcn_ds_permute(dst << 2, lane);
+        R.n2 = n2;
+        R.Qtot = R.QF0 + 4 * (2 * n2 + (ng - n2));
+    }
     R.QR = R.red ? (nv - 2) * C::NQT : 0;         // load-only points (reduced rule)
     R.lane = lane;
     R.c = c;
@@ -869,7 +912,6 @@ __device__ __forceinline__ void row_body(const AsmArgs &A, const int c, T *wlds)
     R.ng = ng;
     R.xs = C::LW > 0 ? wlds : nullptr;
     R.gmask = h.gmask;
-    R.gtab = h.gtab;
     R.ex = h.ex;
     R.ey = h.ey;
     R.x0 = readlane_d(h.ex, 0);
