@@ -44,6 +44,7 @@
 #include "asm_common.h"
 #include "kernels.h"
 #include "row_common.h"
+#include "row_f32.h"
 #include "wave.h"
 
 namespace dgp {
@@ -947,7 +948,10 @@ template <typename T>
 constexpr int lw_fused() {
     constexpr int a = lw_mixed<T, 1>(), b = lw_mixed<T, 2>(), c = lw_mixed<T, 3>(), d = lw_mixed<T, 4>();
     constexpr int ab = a > b ? a : b, cd = c > d ? c : d;
-    return ab > cd ? ab : cd;
+    // FP32: also the FP32 row body's table (rows of degree <= 2)
+    constexpr int e = sizeof(T) == 4 ? F32Cfg<2, true>::LW : 0;
+    constexpr int abcd = ab > cd ? ab : cd;
+    return abcd > e ? abcd : e;
 }
 
 template <typename T, bool ADV>
@@ -960,14 +964,32 @@ __global__ void __launch_bounds__(256) k_row2d_fused(AsmArgs A) {
     for (int it = w0; it < A.n_rows; it += nw) {
         const int c = __builtin_amdgcn_readfirstlane(A.rows[it]);
         const int p = __builtin_amdgcn_readfirstlane((int)A.m.cell_p[c]);
+        // FP32 rows of degree <= 2 with the plain rules: the body of the FP32 row
+        // kernel (row_f32.h), as their per-degree launch runs them
+        constexpr bool F32 = sizeof(T) == 4;
         if (p == 4)
             row_body<T, 4, kMaxP, true, ADV>(A, c, wlds);
         else if (p == 3)
             row_body<T, 3, kMaxP, true, ADV>(A, c, wlds);
-        else if (p == 2)
-            row_body<T, 2, kMaxP, true, ADV>(A, c, wlds);
-        else
-            row_body<T, 1, kMaxP, true, ADV>(A, c, wlds);
+        else if (p == 2) {
+            if constexpr (F32) {
+                if (!A.reduced)
+                    row_f32<2, ADV, true>(A, c, wlds);
+                else
+                    row_body<T, 2, kMaxP, true, ADV>(A, c, wlds);
+            } else {
+                row_body<T, 2, kMaxP, true, ADV>(A, c, wlds);
+            }
+        } else {
+            if constexpr (F32) {
+                if (!A.reduced)
+                    row_f32<1, ADV, true>(A, c, wlds);
+                else
+                    row_body<T, 1, kMaxP, true, ADV>(A, c, wlds);
+            } else {
+                row_body<T, 1, kMaxP, true, ADV>(A, c, wlds);
+            }
+        }
         wave_sync();  // the next row reuses the wave's LDS region
     }
 }
@@ -1037,7 +1059,7 @@ static size_t spill_bytes(int alt, bool adv) {
 }
 
 size_t row2d_spill_bytes(int precision, int p, bool mixed, int alt, bool adv) {
-    if (precision == 1 && !mixed && (p == 1 || p == 2)) return row2d_f32_spill_bytes(p, alt, adv);  // plain rules
+    if (precision == 1 && (p == 1 || p == 2)) return row2d_f32_spill_bytes(p, mixed, alt, adv);  // plain rules
 #define DGP_SP(T, PP) \
     if (p == PP) return mixed ? spill_bytes<T, PP, kMaxP, true>(alt, adv) : spill_bytes<T, PP, PP, false>(alt, adv);
     if (precision == 0) {
@@ -1050,8 +1072,8 @@ size_t row2d_spill_bytes(int precision, int p, bool mixed, int alt, bool adv) {
 }
 
 bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, int alt, hipStream_t st) {
-    if (row2d_f32_applies(a, precision, p, mixed)) {
-        launch_row2d_f32(a, p, alt, st);
+    if (row2d_f32_applies(a, precision, p)) {
+        launch_row2d_f32(a, p, mixed, alt, st);
         return true;
     }
 #define DGP_ROW(T, PP)                                      \

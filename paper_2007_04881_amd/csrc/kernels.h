@@ -26,11 +26,12 @@ void launch_row2d_fused(const AsmArgs &a, int precision, hipStream_t st);
 // launch_row2d(.., precision, p, mixed, alt, ..) runs for a problem with (adv) or
 // without advection-reaction terms
 size_t row2d_spill_bytes(int precision, int p, bool mixed, int alt, bool adv);
-// The FP32 row kernel for meshes of one degree p <= 2 with the plain rules
-// (launch_row2d takes it whenever row2d_f32_applies); same outputs within FP32 rounding.
-bool row2d_f32_applies(const AsmArgs &a, int precision, int p, bool mixed);
-void launch_row2d_f32(const AsmArgs &a, int p, int alt, hipStream_t st);
-size_t row2d_f32_spill_bytes(int p, int alt, bool adv);
+// The FP32 row kernel for rows of degree p <= 2 with the plain rules, on meshes
+// of one degree or (mixed) among neighbours of any degree (launch_row2d takes
+// it whenever row2d_f32_applies); same outputs within FP32 rounding.
+bool row2d_f32_applies(const AsmArgs &a, int precision, int p);
+void launch_row2d_f32(const AsmArgs &a, int p, bool mixed, int alt, hipStream_t st);
+size_t row2d_f32_spill_bytes(int p, bool mixed, int alt, bool adv);
 
 // ---- polyhedral (3D) meshes
 // Geometry, face groups and row counts of every cell, then the tile scan.
