@@ -284,8 +284,10 @@ def mixed_degree_study(D, torch, steps, warmup):
         tname = "float" if prec == D.F32 else "double"
         row = choice[1 if prec == D.F32 else 0]
         fused = bool(row[0])
+        per_degree = (f"k_row2d_f32<p,false,*,true> (p = 1, 2) + k_row2d<float,p,4,true,false,*> (p = 3, 4)"
+                      if prec == D.F32 else "k_row2d<double,p,4,true,false,*>")
         kname = (f"k_row2d_fused<{tname},false> (one persistent launch over every bin)" if fused else
-                 f"k_row2d<{tname},p,4,true,false,*> (one launch per degree, summed)")
+                 f"{per_degree} (one launch per degree, summed)")
         out[name] = {"ms_per_step": ms, "block_nnz_per_s": info.nnzb / (ms * 1e-3),
                      "kernel_ms": {"prep": prep_ms, "assemble": asm_ms},
                      "autotuned": {"single_launch": fused, "launch_cfg_by_degree": row[1:],
