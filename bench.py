@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-KERNEL_SOURCES = ["assemble_f32.hip", "row_common.h", "asm_common.h", "dgp_common.h", "rules_data.h", "wave.h"]
+KERNEL_SOURCES = ["assemble_f32.hip", "row_f32.h", "row_common.h", "asm_common.h", "dgp_common.h", "rules_data.h", "wave.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_row2d_f32_p2_voronoi16384.json")
 
 
