@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(256, 2) k_vol3d(Asm3Args A) {
     const DevProblem &pr = A.pr;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wid = blockIdx.x * 4 + wv;
+    const int wid = xcd_block(blockIdx.x, gridDim.x) * 4 + wv;  // XCD x: one contiguous range of the row order
     if (wid >= A.n_rows) return;
     const int c = A.rows ? __builtin_amdgcn_readfirstlane(A.rows[wid]) : wid;
     Row3 R;
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) k_face3d(Asm3Ar
     const DevProblem &pr = A.pr;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wid = blockIdx.x * 4 + wv;
+    const int wid = xcd_block(blockIdx.x, gridDim.x) * 4 + wv;  // XCD x: one contiguous range of the row order
     if (wid >= A.n_rows) return;
     const int c = A.rows ? __builtin_amdgcn_readfirstlane(A.rows[wid]) : wid;
     Row3 R;

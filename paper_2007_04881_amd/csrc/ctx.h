@@ -27,6 +27,7 @@ struct dgp_ctx {
     int64_t rows_off[dgp::kMaxP + 2] = {};  // group of degree p: rows_by_p[rows_off[p] .. rows_off[p + 1])
     int32_t *rows_sub = nullptr;  // 2D: element ids by (degree, fan sub-triangle count), stable; same rows_off
     int32_t *rows_lpt = nullptr;  // 2D mixed degrees: all element ids by (degree, sub-triangles) descending
+    int32_t *rows_3d = nullptr;   // 3D, one degree: element ids along a Morton curve of their first vertex
     int64_t n_boundary_faces = 0;
     int max_dup2d = 1;            // 2D: most edges one cell shares with one neighbour
     std::vector<void *> mesh_bufs;

@@ -2,6 +2,7 @@
 // validation, device buffers, kernel launches, graph capture and timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -50,6 +51,8 @@ static void free_mesh(dgp_ctx *c) {
     c->rows_sub = nullptr;
     if (c->rows_lpt) (void)hipFree(c->rows_lpt);
     c->rows_lpt = nullptr;
+    if (c->rows_3d) (void)hipFree(c->rows_3d);
+    c->rows_3d = nullptr;
     dgp_free_approach1(c);
     for (void *p : {(void *)c->row_ptr, (void *)c->col_idx, (void *)c->val_ptr, (void *)c->dof_ptr, c->work})
         if (p) (void)hipFree(p);
@@ -569,13 +572,58 @@ static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
     }
     HIPCHK(ctx, hipMemset(ctx->work, 0, work_bytes));
     layout3d(N, n_cf, ctx->n_tiles, static_cast<char *>(ctx->work), &ctx->prep3);
-    if (pmin != pmax) {
+    // the assembly takes the elements along a Morton curve of their first
+    // vertex: a wave's neighbours in time are neighbours in space, so the
+    // faces and vertices they share are read through one XCD's L2 (the ids
+    // of agglomerated polyhedra carry no spatial order); rows are still
+    // written at their own ids, so the output does not depend on the order
+    std::vector<int32_t> morton((size_t)N);
+    {
+        double lo[3] = {m->x[0], m->y[0], m->z[0]}, hi[3] = {lo[0], lo[1], lo[2]};
+        for (int64_t v = 0; v < V; ++v) {
+            const double q[3] = {m->x[v], m->y[v], m->z[v]};
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = q[k] < lo[k] ? q[k] : lo[k];
+                hi[k] = q[k] > hi[k] ? q[k] : hi[k];
+            }
+        }
+        std::vector<std::pair<uint32_t, int32_t>> key((size_t)N);
+        for (int64_t c = 0; c < N; ++c) {
+            const int64_t v = m->cell_vtx[m->cell_ptr[c]];
+            const double q[3] = {m->x[v], m->y[v], m->z[v]};
+            uint32_t code = 0;
+            uint32_t b[3];
+            for (int k = 0; k < 3; ++k) {
+                const double t = hi[k] > lo[k] ? (q[k] - lo[k]) / (hi[k] - lo[k]) : 0.0;
+                b[k] = (uint32_t)std::fmin(1023.0, std::fmax(0.0, t * 1024.0));
+            }
+            for (int bit = 9; bit >= 0; --bit)
+                for (int k = 0; k < 3; ++k) code = (code << 1) | ((b[k] >> bit) & 1u);
+            key[(size_t)c] = {code, (int32_t)c};
+        }
+        std::stable_sort(key.begin(), key.end(),
+                         [](const std::pair<uint32_t, int32_t> &a, const std::pair<uint32_t, int32_t> &b) {
+                             return a.first < b.first;
+                         });
+        for (int64_t i = 0; i < N; ++i) morton[(size_t)i] = key[(size_t)i].second;
+    }
+    if (pmin == pmax) {
+        if (hipMalloc(&ctx->rows_3d, sizeof(int32_t) * (size_t)N) != hipSuccess) {
+            free_mesh(ctx);
+            return fail(ctx, DGP_ENOMEM, "row order");
+        }
+        HIPCHK(ctx, hipMemcpy(ctx->rows_3d, morton.data(), sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice));
+    } else {
         std::vector<int32_t> rows((size_t)N);
         int64_t cnt[kMaxP + 2] = {};
         for (int64_t c = 0; c < N; ++c) cnt[m->cell_p[c] + 1] += 1;
         for (int p = 1; p <= kMaxP + 1; ++p) cnt[p] += cnt[p - 1];
         for (int p = 0; p <= kMaxP + 1; ++p) ctx->rows_off[p] = cnt[p];
-        for (int64_t c = 0; c < N; ++c) rows[(size_t)cnt[m->cell_p[c]]++] = (int32_t)c;
+        // each degree's rows along the curve too
+        for (int64_t i = 0; i < N; ++i) {
+            const int32_t c = morton[(size_t)i];
+            rows[(size_t)cnt[m->cell_p[c]]++] = c;
+        }
         if (hipMalloc(&ctx->rows_by_p, sizeof(int32_t) * (size_t)N) != hipSuccess) {
             free_mesh(ctx);
             return fail(ctx, DGP_ENOMEM, "row groups");
@@ -714,7 +762,7 @@ static dgp_status launch_assembly3d(dgp_ctx *ctx, const DevProblem &dp, int prec
     a.rhs = rhs;
     a.values = values;
     a.write_pattern = write_pattern;
-    a.rows = nullptr;
+    a.rows = ctx->rows_3d;
     a.n_rows = (int32_t)ctx->n_cells;
     if (ctx->p_uniform > 0) {
         if (!launch_row3d(a, precision, ctx->p_uniform, st))
