@@ -197,8 +197,8 @@ dgp_status dgp_run(dgp_ctx *ctx, const dgp_problem *prob, int precision, int rul
  * instead of the buffer the context allocates at upload.  Same arguments,
  * results bit-identical to dgp_run; the call itself allocates and frees
  * nothing.  Fails with DGP_EUNSUPPORTED if the mesh needs more scratch than
- * the array holds (2D: 64 B per element, 36 B per loop edge, 16 B per element
- * of row counts, 40 B per tile of 32 elements).  All calls on one device share
+ * the array holds (2D: 128 B per element of geometry and 16 B of row counts,
+ * 36 B per loop edge, 16 B per face, 40 B per tile of 32 elements).  All calls on one device share
  * that device's array: calls that overlap on one device (several streams or
  * contexts, host threads) race and must be serialised by the caller.
  * Asynchronous.  Afterwards dgp_time_kernels and dgp_autotune report
