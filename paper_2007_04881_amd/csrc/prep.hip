@@ -378,9 +378,26 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int32_t *__restrict__ 
     const int t = threadIdx.x;
     const int per = (n_tiles + 1023) / 1024;
     const int a = t * per, b = min(a + per, n_tiles);
+    // the run's first KC tile sums are loaded together (one 16-byte load each)
+    // and kept for the write-back; longer runs read the rest twice
+    constexpr int KC = 16;
+    const int4 *ts = reinterpret_cast<const int4 *>(tile_sum);
+    int4 keep[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) keep[k] = a + k < b ? ts[a + k] : make_int4(0, 0, 0, 0);
     int64_t run[3] = {0, 0, 0};
-    for (int i = a; i < b; ++i)
-        for (int q = 0; q < 3; ++q) run[q] += tile_sum[4 * i + q];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        run[0] += keep[k].x;
+        run[1] += keep[k].y;
+        run[2] += keep[k].z;
+    }
+    for (int i = a + KC; i < b; ++i) {
+        const int4 v = ts[i];
+        run[0] += v.x;
+        run[1] += v.y;
+        run[2] += v.z;
+    }
     for (int q = 0; q < 3; ++q) sh[q][t] = run[q];
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -393,11 +410,25 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int32_t *__restrict__ 
     }
     int64_t acc[3];
     for (int q = 0; q < 3; ++q) acc[q] = sh[q][t] - run[q];
-    for (int i = a; i < b; ++i)
-        for (int q = 0; q < 3; ++q) {
-            tile_off[3 * i + q] = acc[q];
-            acc[q] += tile_sum[4 * i + q];
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        if (a + k < b) {
+            tile_off[3 * (a + k) + 0] = acc[0];
+            tile_off[3 * (a + k) + 1] = acc[1];
+            tile_off[3 * (a + k) + 2] = acc[2];
+            acc[0] += keep[k].x;
+            acc[1] += keep[k].y;
+            acc[2] += keep[k].z;
         }
+    for (int i = a + KC; i < b; ++i) {
+        const int4 v = ts[i];
+        tile_off[3 * i + 0] = acc[0];
+        tile_off[3 * i + 1] = acc[1];
+        tile_off[3 * i + 2] = acc[2];
+        acc[0] += v.x;
+        acc[1] += v.y;
+        acc[2] += v.z;
+    }
     if (t == 1023)
         for (int q = 0; q < 3; ++q) tile_off[3 * n_tiles + q] = sh[q][1023];
 }

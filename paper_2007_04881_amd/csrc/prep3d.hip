@@ -324,8 +324,20 @@ __global__ void __launch_bounds__(1024) k_scan3d(int n_tiles, const int64_t *__r
     const int t = threadIdx.x;
     const int per = (n_tiles + 1023) / 1024;
     const int a = t * per, b = min(a + per, n_tiles);
+    // the run's first KC tile sums are loaded together and kept for the
+    // write-back; longer runs read the rest twice
+    constexpr int KC = 8;
+    int64_t keep[KC][3];
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) keep[k][q] = a + k < b ? tile_sum[3 * (a + k) + q] : 0;
     int64_t run[3] = {0, 0, 0};
-    for (int i = a; i < b; ++i)
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) run[q] += keep[k][q];
+    for (int i = a + KC; i < b; ++i)
         for (int q = 0; q < 3; ++q) run[q] += tile_sum[3 * i + q];
     for (int q = 0; q < 3; ++q) sh[q][t] = run[q];
     __syncthreads();
@@ -339,7 +351,15 @@ __global__ void __launch_bounds__(1024) k_scan3d(int n_tiles, const int64_t *__r
     }
     int64_t acc[3];
     for (int q = 0; q < 3; ++q) acc[q] = sh[q][t] - run[q];
-    for (int i = a; i < b; ++i)
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        if (a + k < b)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                tile_off[3 * (a + k) + q] = acc[q];
+                acc[q] += keep[k][q];
+            }
+    for (int i = a + KC; i < b; ++i)
         for (int q = 0; q < 3; ++q) {
             tile_off[3 * i + q] = acc[q];
             acc[q] += tile_sum[3 * i + q];
