@@ -53,7 +53,7 @@ size_t spill_p(int alt, bool adv) {
 }  // namespace
 
 bool row2d_f32_applies(const AsmArgs &a, int precision, int p) {
-    return precision == 1 && !a.reduced && (p == 1 || p == 2);
+    return precision == 1 && !a.reduced && a.pr.u_kind == 0 && (p == 1 || p == 2);
 }
 
 void launch_row2d_f32(const AsmArgs &a, int p, bool mixed, int alt, hipStream_t st) {

@@ -964,8 +964,8 @@ __global__ void __launch_bounds__(256) k_row2d_fused(AsmArgs A) {
     for (int it = w0; it < A.n_rows; it += nw) {
         const int c = __builtin_amdgcn_readfirstlane(A.rows[it]);
         const int p = __builtin_amdgcn_readfirstlane((int)A.m.cell_p[c]);
-        // FP32 rows of degree <= 2 with the plain rules: the body of the FP32 row
-        // kernel (row_f32.h), as their per-degree launch runs them
+        // FP32 rows of degree <= 2 with the plain rules and the sine solution: the
+        // body of the FP32 row kernel (row_f32.h), as their per-degree launch runs them
         constexpr bool F32 = sizeof(T) == 4;
         if (p == 4)
             row_body<T, 4, kMaxP, true, ADV>(A, c, wlds);
@@ -973,7 +973,7 @@ __global__ void __launch_bounds__(256) k_row2d_fused(AsmArgs A) {
             row_body<T, 3, kMaxP, true, ADV>(A, c, wlds);
         else if (p == 2) {
             if constexpr (F32) {
-                if (!A.reduced)
+                if (!A.reduced && A.pr.u_kind == 0)
                     row_f32<2, ADV, true>(A, c, wlds);
                 else
                     row_body<T, 2, kMaxP, true, ADV>(A, c, wlds);
@@ -982,7 +982,7 @@ __global__ void __launch_bounds__(256) k_row2d_fused(AsmArgs A) {
             }
         } else {
             if constexpr (F32) {
-                if (!A.reduced)
+                if (!A.reduced && A.pr.u_kind == 0)
                     row_f32<1, ADV, true>(A, c, wlds);
                 else
                     row_body<T, 1, kMaxP, true, ADV>(A, c, wlds);
@@ -1058,8 +1058,9 @@ static size_t spill_bytes(int alt, bool adv) {
     return fa.localSizeBytes;
 }
 
-size_t row2d_spill_bytes(int precision, int p, bool mixed, int alt, bool adv) {
-    if (precision == 1 && (p == 1 || p == 2)) return row2d_f32_spill_bytes(p, mixed, alt, adv);  // plain rules
+size_t row2d_spill_bytes(const AsmArgs &a, int precision, int p, bool mixed, int alt) {
+    const bool adv = a.pr.bx != 0.0 || a.pr.by != 0.0 || a.pr.c != 0.0;
+    if (row2d_f32_applies(a, precision, p)) return row2d_f32_spill_bytes(p, mixed, alt, adv);
 #define DGP_SP(T, PP) \
     if (p == PP) return mixed ? spill_bytes<T, PP, kMaxP, true>(alt, adv) : spill_bytes<T, PP, PP, false>(alt, adv);
     if (precision == 0) {

@@ -132,6 +132,9 @@ struct PointData {
 
 // Manufactured data at (x, y) from sin/cos(pi x), sin/cos(pi y); the load uses
 // the closed-form derivatives of a and u.
+// SINES: the caller handles the sine solution only (u_kind 0), so the
+// polynomial branch and its coefficients are left out of its code.
+template <bool SINES = false>
 __device__ __forceinline__ PointData point_data_sc(const DevProblem &pr, double x, double y, double sx, double cx,
                                                    double sy, double cy, bool need_f) {
     PointData d;
@@ -145,7 +148,7 @@ __device__ __forceinline__ PointData point_data_sc(const DevProblem &pr, double 
     } else {
         d.a = pr.a0;
     }
-    if (pr.u_kind == 0) {
+    if (SINES || pr.u_kind == 0) {
         d.u = sx * sy;
         d.ux = kPi * cx * sy;
         d.uy = kPi * sx * cy;
@@ -164,13 +167,14 @@ __device__ __forceinline__ PointData point_data_sc(const DevProblem &pr, double 
 __device__ __forceinline__ bool needs_trig(const DevProblem &pr) { return pr.u_kind == 0 || pr.a1 != 0.0; }
 
 // Manufactured data at (x, y) with sin/cos evaluated directly (exact at integer points).
+template <bool SINES = false>
 __device__ __forceinline__ PointData point_data(const DevProblem &pr, double x, double y, bool need_f) {
     double sx = 0.0, cx = 1.0, sy = 0.0, cy = 1.0;
-    if (needs_trig(pr)) {
+    if (SINES || needs_trig(pr)) {
         sincospi(x, &sx, &cx);
         sincospi(y, &sy, &cy);
     }
-    return point_data_sc(pr, x, y, sx, cx, sy, cy, need_f);
+    return point_data_sc<SINES>(pr, x, y, sx, cx, sy, cy, need_f);
 }
 
 // sin/cos(pi (x0 + d)) from s0 = sin(pi x0), c0 = cos(pi x0) by angle addition,

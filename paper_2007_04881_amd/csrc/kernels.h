@@ -23,12 +23,12 @@ bool launch_row2d(const AsmArgs &a, int precision, int p, bool mixed, int alt, h
 // meshes), dispatching per row to the same body as launch_row2d(.., mixed = true, ..).
 void launch_row2d_fused(const AsmArgs &a, int precision, hipStream_t st);
 // per-lane scratch bytes (register spills) of the row kernel instantiation that
-// launch_row2d(.., precision, p, mixed, alt, ..) runs for a problem with (adv) or
-// without advection-reaction terms
-size_t row2d_spill_bytes(int precision, int p, bool mixed, int alt, bool adv);
-// The FP32 row kernel for rows of degree p <= 2 with the plain rules, on meshes
-// of one degree or (mixed) among neighbours of any degree (launch_row2d takes
-// it whenever row2d_f32_applies); same outputs within FP32 rounding.
+// launch_row2d(a, precision, p, mixed, alt, ..) runs
+size_t row2d_spill_bytes(const AsmArgs &a, int precision, int p, bool mixed, int alt);
+// The FP32 row kernel for rows of degree p <= 2 with the plain rules and the
+// sine manufactured solution, on meshes of one degree or (mixed) among
+// neighbours of any degree (launch_row2d takes it whenever row2d_f32_applies);
+// same outputs within FP32 rounding.
 bool row2d_f32_applies(const AsmArgs &a, int precision, int p);
 void launch_row2d_f32(const AsmArgs &a, int p, bool mixed, int alt, hipStream_t st);
 size_t row2d_f32_spill_bytes(int p, bool mixed, int alt, bool adv);

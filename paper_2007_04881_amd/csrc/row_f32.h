@@ -12,7 +12,9 @@
 //  * a point's lane fetches its vertices' or its edge's values (ds_bpermute)
 //    and forms its box coordinates and coefficients in FP32; the manufactured
 //    data (a, f, boundary values) stay FP64 (sin / cos by angle addition from
-//    the box centre);
+//    the box centre), for the sine solution only (problems with the
+//    polynomial solution take the general row kernel: its coefficients would
+//    hold scalar registers through the whole row);
 //  * a transposed per-wave LDS table holds, per basis function, the test
 //    terms of every point of the pass (columns 3 lane + a), then the
 //    neighbour's trial terms (the cross blocks of every edge group of the pass
@@ -54,20 +56,19 @@ struct F32Cfg {
     static constexpr int LW = (2 * NB + 1) * KS;
 };
 
-// The manufactured data at a point given by its offset (px, py) from the box
-// centre (x0, y0), in FP64: sin / cos by angle addition from the centre's values
+// The manufactured data (the sine solution) at a point given by its offset
+// (px, py) from the box centre (x0, y0), in FP64: sin / cos by angle addition from the centre's values
 // when the element is small (near), else directly.  FP64 because the load f is a
 // sum of terms up to tens of times larger than itself (FP32 data put the load
 // rows of elements where f changes sign 6e-5 off).
 __device__ __forceinline__ PointData data_near(const DevProblem &pr, bool near, double x0, double y0, double s0x,
                                                double c0x, double s0y, double c0y, float px, float py, bool need_f) {
     const double x = x0 + double(px), y = y0 + double(py);
-    if (!needs_trig(pr)) return point_data_sc(pr, x, y, 0.0, 1.0, 0.0, 1.0, need_f);
-    if (!near) return point_data(pr, x, y, need_f);
+    if (!near) return point_data<true>(pr, x, y, need_f);
     double sx, cx, sy, cy;
     sincospi_near(s0x, c0x, double(px), &sx, &cx);
     sincospi_near(s0y, c0y, double(py), &sy, &cy);
-    return point_data_sc(pr, x, y, sx, cx, sy, cy, need_f);
+    return point_data_sc<true>(pr, x, y, sx, cx, sy, cy, need_f);
 }
 
 // a + b with its rounding error carried in e (TwoSum, Knuth)
@@ -299,7 +300,7 @@ __device__ __forceinline__ void row_f32(const AsmArgs &A, const int c, float *xs
             if (vol || (epnt && og >= 0))
                 dd = data_near(pr, near, xc, yc, s0x, c0x, s0y, c0y, ppx, ppy, true);
             else if (epnt)
-                dd = point_data(pr, double(ppx), double(ppy), false);
+                dd = point_data<true>(pr, double(ppx), double(ppy), false);
             if (vol) {
                 const float Wa = W * float(dd.a);
                 a0 = Wa * cx2;

@@ -1017,15 +1017,14 @@ dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice) {
         }
         // each configuration of each bin gets an equal share of the budget (at least one launch)
         const float share = (float)budget_ms / (float)(kLaunchCfgs * (nbins > 0 ? nbins : 1));
-        const bool adv = a.pr.bx != 0.0 || a.pr.by != 0.0 || a.pr.c != 0.0;
         for (int b = 0; b < nbins; ++b) {
             const int p = bins[b];
             const bool mixed = ctx->p_uniform <= 0;
             // the larger-occupancy register budget is tried only if it spills at
             // most kAltSpillMax bytes per lane more than the default (large
             // spills write tens of MB per launch; a few dwords can still win)
-            const size_t spill0 = row2d_spill_bytes(ctx->last_precision, p, mixed, 0, adv);
-            const size_t spill1 = row2d_spill_bytes(ctx->last_precision, p, mixed, 1, adv);
+            const size_t spill0 = row2d_spill_bytes(a, ctx->last_precision, p, mixed, 0);
+            const size_t spill1 = row2d_spill_bytes(a, ctx->last_precision, p, mixed, 1);
             float best = 0.0f;
             int best_cfg = 0;
             for (int cfg = 0; cfg < kLaunchCfgs; ++cfg) {
