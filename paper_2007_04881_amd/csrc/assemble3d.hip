@@ -141,7 +141,11 @@ __device__ __forceinline__ void exact3(const DevProblem &pr, const Trig3 &t, con
         gu[2] = kPi * s[0] * s[1] * c[2];
         lap = -3.0 * kPi * kPi * (*u);
     } else {
-        const double *q = pr.u;
+        // read here at an offset (zero) hidden from the compiler, so that the ten
+        // coefficients are not hoisted into scalar registers for the whole kernel
+        int z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        const double *q = pr.u + z;
         *u = q[0] + q[1] * x[0] + q[2] * x[1] + q[3] * x[2] + q[4] * x[0] * x[0] + q[5] * x[1] * x[1] +
              q[6] * x[2] * x[2] + q[7] * x[0] * x[1] + q[8] * x[0] * x[2] + q[9] * x[1] * x[2];
         gu[0] = q[1] + 2 * q[4] * x[0] + q[7] * x[1] + q[8] * x[2];

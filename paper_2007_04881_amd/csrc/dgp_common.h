@@ -154,7 +154,13 @@ __device__ __forceinline__ PointData point_data_sc(const DevProblem &pr, double 
         d.uy = kPi * sx * cy;
         lap = -2.0 * kPi * kPi * d.u;
     } else {
-        const double *c = pr.u;
+        // the coefficients are read here, at an offset (zero) that an empty
+        // scalar move hides from the compiler: plain reads of the kernel
+        // argument would be hoisted to the kernel's start, and the six values
+        // would hold twelve scalar registers through every loop of the caller
+        int z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        const double *c = pr.u + z;
         d.u = c[0] + c[1] * x + c[2] * y + c[4] * x * x + c[5] * y * y + c[7] * x * y;
         d.ux = c[1] + 2.0 * c[4] * x + c[7] * y;
         d.uy = c[2] + 2.0 * c[5] * y + c[7] * x;
