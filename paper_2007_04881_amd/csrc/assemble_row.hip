@@ -51,6 +51,14 @@ namespace dgp {
 
 namespace {
 
+// Row stride (elements) of the matrix-core tables: a lane stores table rows
+// 3 l + a, so with rows of 16 the lanes of one store start 48 elements apart
+// and fall on 4 of the banks (an 8-way conflict per store); with rows of 17
+// they start 51 apart, an odd stride, and every lane of a store has its own
+// bank.  The matrix-instruction reads (16 consecutive columns of 4 rows) then
+// meet at most one 2-way conflict.
+constexpr int kMfStride = 17;
+
 // P: degree of the row's element; PN: largest degree of its neighbours
 template <typename T, int P, int PN>
 struct RowCfg {
@@ -60,7 +68,7 @@ struct RowCfg {
     // MF: the element block is a matrix-core product (p >= 3: 10 x 10 and
     // 15 x 15 blocks fill enough of a 16 x 16 tile); no column slices then
     static constexpr bool MF = P >= 3;
-    static constexpr int MFW = sizeof(T) == 4 ? 2 * 96 * 16 : 2 * 48 * 16;  // LDS table per wave (T elements)
+    static constexpr int MFW = sizeof(T) == 4 ? 2 * 96 * kMfStride : 2 * 48 * kMfStride;  // LDS table per wave (T elements)
     static constexpr int JS = MF ? NB : sizeof(T) == 4 ? (P <= 2 ? NB : P == 3 ? 5 : 3) : (P == 1 ? 3 : P == 2 ? 3 : 2);
     static constexpr int NSL = (NB + JS - 1) / JS;
     static constexpr int ED = MF ? 0 : NB * JS;  // element-block entries per slice held in registers
@@ -88,7 +96,7 @@ struct RowCfg {
     // kernels, whose neighbours may have larger blocks than the row's own; in
     // FP64 the staged trial terms cost those kernels a wave per SIMD: slower)
     static constexpr bool CM = !XL && (P >= 3 || (PN > P && sizeof(T) == 4));
-    static constexpr int CMW = 2 * 3 * FG * 16;  // its table per wave (T elements)
+    static constexpr int CMW = 2 * 3 * FG * kMfStride;  // its table per wave (T elements)
     // VU: edge groups of 4 or 8 lanes (units of 4), by the Gauss points each
     // edge needs (a row of degree < 4 needs 8 only towards degree-4
     // neighbours): 8-lane groups first, each starting on an 8-lane boundary,
@@ -147,25 +155,26 @@ __device__ __forceinline__ void mf_element(T *lds, int lane, const Eval<T, P> &e
     constexpr int NGR = sizeof(T) == 4 ? 2 : 4;  // lane groups staged in turn
     constexpr int LG = 64 / NGR;                 // lanes per group
     constexpr int KR = 3 * LG;                   // rows of u (and of t) per group
-    T *U = lds, *Tt = lds + KR * 16;
+    T *U = lds, *Tt = lds + KR * kMfStride;
 #pragma unroll
     for (int g = 0; g < NGR; ++g) {
         if (lane / LG == g) {
             const int k0 = 3 * (lane % LG);
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                U[(k0 + 0) * 16 + j] = ev.g0[j];
-                U[(k0 + 1) * 16 + j] = ev.g1[j];
-                U[(k0 + 2) * 16 + j] = ev.v[j];
-                Tt[(k0 + 0) * 16 + j] = fmat(pc.a0, ev.g0[j], pc.b0 * ev.v[j]);
-                Tt[(k0 + 1) * 16 + j] = fmat(pc.a1, ev.g1[j], pc.b1 * ev.v[j]);
-                Tt[(k0 + 2) * 16 + j] = fmat(pc.c0, ev.g0[j], fmat(pc.c1, ev.g1[j], pc.c2 * ev.v[j]));
+                U[(k0 + 0) * kMfStride + j] = ev.g0[j];
+                U[(k0 + 1) * kMfStride + j] = ev.g1[j];
+                U[(k0 + 2) * kMfStride + j] = ev.v[j];
+                Tt[(k0 + 0) * kMfStride + j] = fmat(pc.a0, ev.g0[j], pc.b0 * ev.v[j]);
+                Tt[(k0 + 1) * kMfStride + j] = fmat(pc.a1, ev.g1[j], pc.b1 * ev.v[j]);
+                Tt[(k0 + 2) * kMfStride + j] = fmat(pc.c0, ev.g0[j], fmat(pc.c1, ev.g1[j], pc.c2 * ev.v[j]));
             }
         }
         wave_sync();
         const int r = lane >> 4, c = lane & 15;
 #pragma unroll 4
-        for (int s = 0; s < KR / 4; ++s) acc = mfma16(U[(4 * s + r) * 16 + c], Tt[(4 * s + r) * 16 + c], acc);
+        for (int s = 0; s < KR / 4; ++s)
+            acc = mfma16(U[(4 * s + r) * kMfStride + c], Tt[(4 * s + r) * kMfStride + c], acc);
         wave_sync();  // the next group rewrites the table
     }
 }
@@ -400,7 +409,7 @@ __device__ __forceinline__ void cross_mf(const AsmArgs &A, const RowCtx &R, cons
     using C = RowCfg<T, P, PN>;
     constexpr int NB = C::NB, NBN = C::NBN, FG = C::FG, KR = 3 * FG;
     static_assert(KR % 4 == 0 && NB <= 16 && NBN <= 16, "one 16 x 16 tile per cross block");
-    T *U = static_cast<T *>(R.xs), *S = U + KR * 16;
+    T *U = static_cast<T *>(R.xs), *S = U + KR * kMfStride;
     const int lane = R.lane;
     // this lane's trial terms (computed once, stored when its group's turn comes)
     T sv[3][NBN];
@@ -448,14 +457,14 @@ __device__ __forceinline__ void cross_mf(const AsmArgs &A, const RowCtx &R, cons
             const int k0 = 3 * (lane - ql);
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
-                U[(k0 + 0) * 16 + i] = ev.g0[i] * T(kNorm[i]);
-                U[(k0 + 1) * 16 + i] = ev.g1[i] * T(kNorm[i]);
-                U[(k0 + 2) * 16 + i] = ev.v[i] * T(kNorm[i]);
+                U[(k0 + 0) * kMfStride + i] = ev.g0[i] * T(kNorm[i]);
+                U[(k0 + 1) * kMfStride + i] = ev.g1[i] * T(kNorm[i]);
+                U[(k0 + 2) * kMfStride + i] = ev.v[i] * T(kNorm[i]);
             }
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int j = 0; j < NBN; ++j) S[(k0 + a) * 16 + j] = sv[a][j];
+                for (int j = 0; j < NBN; ++j) S[(k0 + a) * kMfStride + j] = sv[a][j];
         }
         wave_sync();
         MfAcc<T> acc = {T(0), T(0), T(0), T(0)};
@@ -463,7 +472,7 @@ __device__ __forceinline__ void cross_mf(const AsmArgs &A, const RowCtx &R, cons
         const int ks = 3 * fgl / 4;  // matrix steps over the group's 3 fgl table rows
 #pragma unroll
         for (int s = 0; s < KR / 4; ++s)
-            if (s < ks) acc = mfma16(U[(4 * s + r4) * 16 + c], S[(4 * s + r4) * 16 + c], acc);
+            if (s < ks) acc = mfma16(U[(4 * s + r4) * kMfStride + c], S[(4 * s + r4) * kMfStride + c], acc);
         wave_sync();  // the next group rewrites the table
         const int nbog = __builtin_amdgcn_readlane(nbo, ql), gvo = __builtin_amdgcn_readlane(gvoff, ql);
 #pragma unroll
