@@ -570,7 +570,7 @@ def main():
                      "valu_issue": valu_issue(cfg, avg["assemble"])},
         "upload_ms": upload_ms,
         "launch_config": {"cfg": cfg, "register_budget": "one more wave per SIMD" if alt else "default",
-                          "row_order": "(degree, sub-triangles) bins" if cfg & 2 else "cell id"},
+                          "row_order": "per XCD range, most sub-triangles first" if cfg & 2 else "cell id"},
     }
     ctx.close()
     if not args.no_reduced:

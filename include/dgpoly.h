@@ -228,10 +228,12 @@ dgp_status dgp_kernel_ms(dgp_ctx *ctx, const char *name, float *ms);
 dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assemble_ms);
 
 /* Launch tuning per degree bin (Section 3.1 groups the elements by p; the
- * upload also sorts each degree's rows by their number of fan sub-triangles,
- * the bins (p, n_sub)).  A 2D launch configuration is cfg = r + 2 s with
- * r = 1 for the row kernel's larger occupancy (one more wave per SIMD, fewer
- * registers) and s = 1 for the rows in (p, n_sub) order instead of id order.
+ * upload also orders each degree's rows a second way: the id order cut into
+ * the eight ranges the launch gives the XCDs, each range sorted by the number
+ * of fan sub-triangles, largest first).  A 2D launch configuration is
+ * cfg = r + 2 s with r = 1 for the row kernel's larger occupancy (one more
+ * wave per SIMD, fewer registers) and s = 1 for the rows in that second order
+ * instead of id order.
  * For the last dgp_run / dgp_assemble on a 2D mesh with plain rules, times the
  * four configurations of each degree bin within about budget_ms milliseconds of
  * device time and keeps the fastest for later launches of that precision and

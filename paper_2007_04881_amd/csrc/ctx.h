@@ -25,7 +25,7 @@ struct dgp_ctx {
     int p_max = 0;
     int32_t *rows_by_p = nullptr;      // mixed degrees: element ids grouped by degree (stable)
     int64_t rows_off[dgp::kMaxP + 2] = {};  // group of degree p: rows_by_p[rows_off[p] .. rows_off[p + 1])
-    int32_t *rows_sub = nullptr;  // 2D: element ids by (degree, fan sub-triangle count), stable; same rows_off
+    int32_t *rows_sub = nullptr;  // 2D: element ids by degree, then per XCD range most fan sub-triangles first; same rows_off
     int32_t *rows_lpt = nullptr;  // 2D mixed degrees: all element ids by (degree, sub-triangles) descending
     int32_t *rows_3d = nullptr;   // 3D, one degree: element ids along a Morton curve of their first vertex
     int64_t n_boundary_faces = 0;

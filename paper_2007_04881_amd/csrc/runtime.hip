@@ -414,17 +414,33 @@ dgp_status dgp_mesh_upload(dgp_ctx *ctx, const dgp_mesh_desc *m) {
         HIPCHK(ctx, hipMemcpy(ctx->rows_lpt, rows.data(), sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice));
     }
     {
-        // the bins (p, n_sub) of Section 3.1's grouping refined by the number of
-        // fan sub-triangles n_sub = n_v - 2: element ids sorted by that key,
-        // stable in id (one of the two row orders dgp_autotune chooses from)
-        constexpr int NS = kMaxFaces2D;
-        std::vector<int64_t> bc((size_t)(kMaxP + 1) * NS + 1, 0);
-        auto key = [&](int64_t c) { return (int64_t)m->cell_p[c] * NS + (m->cell_ptr[c + 1] - m->cell_ptr[c] - 2); };
-        for (int64_t c = 0; c < N; ++c) bc[(size_t)key(c) + 1] += 1;
-        for (size_t k = 1; k < bc.size(); ++k) bc[k] += bc[k - 1];
-        for (int p = 0; p <= kMaxP + 1; ++p) ctx->rows_off[p] = bc[(size_t)p * NS];
+        // the second row order dgp_autotune chooses from: the rows of each degree
+        // (Section 3.1's grouping) in id order, cut into the eight ranges that a
+        // launch over them gives the XCDs (xcd_block: XCD x runs a contiguous
+        // range of blocks, in order), each range sorted by the number of fan
+        // sub-triangles n_sub = n_v - 2, largest first (stable in id).  Every
+        // XCD keeps the rows, and the cache lines, of the id order but starts
+        // its costliest rows first, so that the launch does not end on them.
+        std::vector<int64_t> pc((size_t)kMaxP + 2, 0);
+        for (int64_t c = 0; c < N; ++c) pc[(size_t)m->cell_p[c] + 1] += 1;
+        for (int p = 1; p <= kMaxP + 1; ++p) pc[(size_t)p] += pc[(size_t)p - 1];
+        for (int p = 0; p <= kMaxP + 1; ++p) ctx->rows_off[p] = pc[(size_t)p];
         std::vector<int32_t> rows((size_t)N);
-        for (int64_t c = 0; c < N; ++c) rows[(size_t)bc[(size_t)key(c)]++] = (int32_t)c;
+        {
+            std::vector<int64_t> pos(pc.begin(), pc.end());
+            for (int64_t c = 0; c < N; ++c) rows[(size_t)pos[(size_t)m->cell_p[c]]++] = (int32_t)c;
+        }
+        auto nsub = [&](int32_t c) { return m->cell_ptr[c + 1] - m->cell_ptr[c] - 2; };
+        for (int p = 0; p <= kMaxP; ++p) {
+            const int64_t o = pc[(size_t)p], n = pc[(size_t)p + 1] - o;
+            const int64_t nb = (n + 3) / 4, q = nb >> 3, r = nb & 7;  // as xcd_block over nb blocks of 4 rows
+            for (int64_t x = 0; x < 8; ++x) {
+                const int64_t b0 = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q, bn = x < r ? q + 1 : q;
+                const int64_t lo = o + std::min(4 * b0, n), hi = o + std::min(4 * (b0 + bn), n);
+                std::stable_sort(rows.begin() + lo, rows.begin() + hi,
+                                 [&](int32_t a, int32_t b) { return nsub(a) > nsub(b); });
+            }
+        }
         if (hipMalloc(&ctx->rows_sub, sizeof(int32_t) * (size_t)N) != hipSuccess) {
             free_mesh(ctx);
             return fail(ctx, DGP_ENOMEM, "row bins");
@@ -781,7 +797,7 @@ static dgp_status launch_assembly3d(dgp_ctx *ctx, const DevProblem &dp, int prec
 }
 
 // The rows of degree p for launch configuration cfg: id order (uniform degree:
-// all rows, no list) or, with bit 1, the (degree, sub-triangle count) order.
+// all rows, no list) or, with bit 1, per XCD range most sub-triangles first.
 static void row_range(const dgp_ctx *ctx, AsmArgs &a, int p, int cfg) {
     const int64_t o = ctx->rows_off[p], n = ctx->rows_off[p + 1] - o;
     if (cfg & 2)
