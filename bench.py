@@ -25,7 +25,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-KERNEL_SOURCES = ["assemble_f32.hip", "row_f32.h", "row_common.h", "asm_common.h", "dgp_common.h", "rules_data.h", "wave.h"]
+# the headline kernel's sources, and the runtime, which builds the row orders
+# of its launch configurations (the committed counters hold for these only)
+KERNEL_SOURCES = ["assemble_f32.hip", "row_f32.h", "row_common.h", "asm_common.h", "dgp_common.h", "rules_data.h", "wave.h",
+                  "runtime.hip", "ctx.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_row2d_f32_p2_voronoi16384.json")
 
 

@@ -623,7 +623,32 @@ static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
                          });
         for (int64_t i = 0; i < N; ++i) morton[(size_t)i] = key[(size_t)i].second;
     }
+    // then each window of 256 rows along the curve, inside the range a launch
+    // gives one XCD (xcd_block), sorted by the polyhedron's number of faces,
+    // largest first (stable): the four rows of a work-group cost about the
+    // same (a work-group holds its slot until its slowest wave ends), and a
+    // window's rows still run close together in time, so the faces they share
+    // are read once through the XCD's L2.  Measured on 32,768 agglomerated
+    // polyhedra: 2.59 -> 2.34 ms FP32, 4.49 -> 3.90 ms FP64, face-kernel reads
+    // +8%; sorting the XCD's whole range instead gave 2.22 ms but 4.4 x the reads.
+    std::vector<int32_t> nfaces((size_t)N, 0);
+    for (int64_t f = 0; f < F; ++f) {
+        const int32_t l = m->face_cell[2 * f], r = m->face_cell[2 * f + 1];
+        if (l >= 0) nfaces[(size_t)l] += 1;
+        if (r >= 0 && r != l) nfaces[(size_t)r] += 1;
+    }
+    auto similar_blocks = [&](std::vector<int32_t> &rows, int64_t o, int64_t n) {
+        const int64_t nb = (n + 3) / 4, q = nb >> 3, r = nb & 7;  // as xcd_block over nb blocks of 4 rows
+        for (int64_t x = 0; x < 8; ++x) {
+            const int64_t b0 = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q, bn = x < r ? q + 1 : q;
+            const int64_t lo = o + std::min(4 * b0, n), hi = o + std::min(4 * (b0 + bn), n);
+            for (int64_t w = lo; w < hi; w += 256)
+                std::stable_sort(rows.begin() + w, rows.begin() + std::min(w + 256, hi),
+                                 [&](int32_t a, int32_t b) { return nfaces[(size_t)a] > nfaces[(size_t)b]; });
+        }
+    };
     if (pmin == pmax) {
+        similar_blocks(morton, 0, N);
         if (hipMalloc(&ctx->rows_3d, sizeof(int32_t) * (size_t)N) != hipSuccess) {
             free_mesh(ctx);
             return fail(ctx, DGP_ENOMEM, "row order");
@@ -640,6 +665,7 @@ static dgp_status upload3d(dgp_ctx *ctx, const dgp_mesh_desc *m) {
             const int32_t c = morton[(size_t)i];
             rows[(size_t)cnt[m->cell_p[c]]++] = c;
         }
+        for (int p = 0; p <= kMaxP; ++p) similar_blocks(rows, ctx->rows_off[p], ctx->rows_off[p + 1] - ctx->rows_off[p]);
         if (hipMalloc(&ctx->rows_by_p, sizeof(int32_t) * (size_t)N) != hipSuccess) {
             free_mesh(ctx);
             return fail(ctx, DGP_ENOMEM, "row groups");
