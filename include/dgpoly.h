@@ -250,7 +250,9 @@ dgp_status dgp_time_kernels(dgp_ctx *ctx, int reps, float *prep_ms, float *assem
 dgp_status dgp_autotune(dgp_ctx *ctx, int budget_ms, int32_t *choice);
 
 /* Set the 2D launch configuration cfg (0..3, as for dgp_autotune) of one
- * precision and degree without timing, for reproducible launches; p = 0 sets
+ * precision and degree without timing, for reproducible launches (a new
+ * context starts every degree at cfg 2: the default register budget, rows in
+ * the second order); p = 0 sets
  * how meshes of mixed degree are launched: cfg 0 one launch per degree, cfg 1
  * one persistent launch over every (degree, sub-triangle count) bin, the
  * costliest bins first (the same per-row arithmetic: bit-identical results).

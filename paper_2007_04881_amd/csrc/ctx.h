@@ -74,8 +74,11 @@ struct dgp_ctx {
 
     // register-budget variant of the 2D row kernel per [precision][degree] (dgp_autotune)
     // 2D launch configuration per [FP64, FP32][degree]: bit 0 = the row kernel's
-    // register budget (one more wave per SIMD), bit 1 = rows in rows_sub order
-    int8_t row_cfg[2][dgp::kMaxP + 1] = {};
+    // register budget (one more wave per SIMD), bit 1 = rows in rows_sub order;
+    // until dgp_autotune or dgp_set_launch, 2 (the default budget, rows_sub
+    // order: the faster order on every workload measured)
+    int8_t row_cfg[2][dgp::kMaxP + 1] = {{2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}};
+    static_assert(dgp::kMaxP == 4, "one initial entry per degree");
     // mixed-degree 2D meshes: one persistent launch over every degree bin (1) or
     // one launch per degree (0), per [FP64, FP32]
     int8_t fused[2] = {0, 0};
