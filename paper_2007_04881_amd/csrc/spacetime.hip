@@ -51,6 +51,11 @@ constexpr StIdx make_st_idx() {
             }
     return r;
 }
+// The index table of degree P as one object in device memory: a
+// function-local constexpr copy indexed by a run-time basis number is built in
+// private memory (scratch) on every call
+template <int P>
+__device__ constexpr StIdx kStIdx = make_st_idx<P>();
 
 template <typename T, int P>
 struct StCfg {
@@ -73,7 +78,7 @@ struct StEval {
     static constexpr int NB = StCfg<T, P>::NB;
     T v[NB], dx[NB], dy[NB], dt[NB];
     __device__ __forceinline__ void at(T xi, T eta, T zeta) {
-        constexpr StIdx I = make_st_idx<P>();
+        const StIdx &I = kStIdx<P>;
         T Lx[P + 1], dLx[P + 1], Ly[P + 1], dLy[P + 1], Lt[P + 1], dLt[P + 1];
         legendre<T, P>(xi, Lx, dLx);
         legendre<T, P>(eta, Ly, dLy);
@@ -91,7 +96,7 @@ struct StEval {
 // sqrt((2a+1)(2b+1)(2c+1)) of basis function i
 template <int P>
 __device__ __forceinline__ double st_norm(int i) {
-    constexpr StIdx I = make_st_idx<P>();
+    const StIdx &I = kStIdx<P>;
     return sqrt(double((2 * I.a[i] + 1) * (2 * I.b[i] + 1) * (2 * I.c[i] + 1)));
 }
 
@@ -207,7 +212,7 @@ __global__ void __launch_bounds__(64) k_row_st(StArgs A) {
                     double uprev;
                     if (A.prev) {
                         // the previous slab's solution at its top (t0): P_c(1) = 1 in its box
-                        constexpr StIdx I = make_st_idx<P>();
+                        const StIdx &I = kStIdx<P>;
                         T Lx[P + 1], dLx[P + 1], Ly[P + 1], dLy[P + 1];
                         legendre<T, P>(T(((X0 - g.lox) - (g.hix - X0) + 2.0 * dx) * ihx), Lx, dLx);
                         legendre<T, P>(T(((Y0 - g.loy) - (g.hiy - Y0) + 2.0 * dy) * ihy), Ly, dLy);
